@@ -1,0 +1,204 @@
+"""ctypes wrapper of the CPU oracle (``smcx_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark call this module; the product path never imports it.  It
+imports nothing from the HIP package either.
+
+Every function takes and returns numpy arrays.  The C source documents which
+passage of the paper each routine follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "smcx_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+BCC, FCC = 0, 1
+MAXZ = 24
+
+TIE_DTYPE = np.dtype([("replica", "<i4"), ("sweep", "<u4"), ("site", "<i8"),
+                      ("decision", "<i4"), ("pad", "<i4")])
+TRACE_DTYPE = np.dtype([("a", "<i8"), ("b", "<i8"), ("dE", "<f8"), ("k", "<i4"),
+                        ("accepted", "<i4")])
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (binary64, no contraction, OpenMP)."""
+    if force or not os.path.exists(LIB):
+        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        p = C.c_void_p
+        i32, i64, u32, u64, dbl = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+        L.or_shells.argtypes = [C.c_int, C.c_int, p, p]
+        L.or_lmin.argtypes = [C.c_int, C.c_int, C.c_int]
+        L.or_partition.argtypes = [C.c_int, C.c_int, p]
+        L.or_philox4x32_10.argtypes = [p, p, p]
+        L.or_philox4x32_10.restype = None
+        L.or_pair_counts.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p]
+        L.or_energy.argtypes = [C.c_int, C.c_int, p, p]
+        L.or_energy.restype = dbl
+        L.or_sro.argtypes = [C.c_int, C.c_int, p, p, p]
+        L.or_delta_e.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, i64, i32, p, p]
+        L.or_single_trial.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, u64, u32, u32, i64, dbl]
+        L.or_run.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, p, p, u64, u32, u32, i32, p, p,
+                             i32, p, p, i32, p, p, i64, i32]
+        L.or_max_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dims(L) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(L, dtype=np.int32).reshape(3))
+
+
+def shells(lattice: int, S: int):
+    """Return (Z[S], list of S arrays of shape (Z_s, 3)) for the first S shells."""
+    Z = np.zeros(4, np.int32)
+    d = np.zeros((4, MAXZ, 3), np.int32)
+    rc = lib().or_shells(lattice, S, _ptr(Z), _ptr(d))
+    if rc != 0:
+        raise ValueError("or_shells failed")
+    return Z[:S].copy(), [d[s, :Z[s]].copy() for s in range(S)]
+
+
+def lmin(lattice: int, S: int, liz: bool = False) -> int:
+    return int(lib().or_lmin(lattice, S, 1 if liz else 0))
+
+
+def partition(L: int, ell: int) -> np.ndarray:
+    sizes = np.zeros(max(L, 1), np.int32)
+    n = lib().or_partition(L, ell, _ptr(sizes))
+    if n < 0:
+        raise ValueError("bad partition request")
+    return sizes[:n].copy()
+
+
+def default_cells(dims, ell: int):
+    """Per-axis cell edges by the default rule, as a list of three arrays."""
+    return [partition(int(L), ell) for L in dims]
+
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(4))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(2))
+    out = np.zeros(4, np.uint32)
+    lib().or_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def pair_counts(lattice: int, dims, K: int, S: int, occ: np.ndarray) -> np.ndarray:
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    Cn = np.zeros((S, K, K), np.int64)
+    rc = lib().or_pair_counts(lattice, _ptr(_dims(dims)), K, S, _ptr(occ), _ptr(Cn))
+    if rc != 0:
+        raise ValueError("or_pair_counts failed")
+    return Cn
+
+
+def energy(Cn: np.ndarray, V: np.ndarray) -> float:
+    S, K, _ = Cn.shape
+    Cn = np.ascontiguousarray(Cn, dtype=np.int64)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    return float(lib().or_energy(K, S, _ptr(Cn), _ptr(V)))
+
+
+def sro(Cn: np.ndarray, Z) -> np.ndarray:
+    S, K, _ = Cn.shape
+    Cn = np.ascontiguousarray(Cn, dtype=np.int64)
+    Zs = np.ascontiguousarray(np.asarray(Z, dtype=np.int32))
+    alpha = np.zeros((S, K, K), np.float64)
+    rc = lib().or_sro(K, S, _ptr(Zs), _ptr(Cn), _ptr(alpha))
+    if rc != 0:
+        raise ValueError("or_sro failed (absent species?)")
+    return alpha
+
+
+def delta_e(lattice, dims, K, S, occ, V, a: int, k: int):
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    dE = np.zeros(1, np.float64)
+    b = np.zeros(1, np.int64)
+    rc = lib().or_delta_e(lattice, _ptr(_dims(dims)), K, S, _ptr(occ), _ptr(V), a, k, _ptr(dE),
+                          _ptr(b))
+    if rc != 0:
+        raise ValueError("or_delta_e failed")
+    return float(dE[0]), int(b[0])
+
+
+def single_trial(lattice, dims, K, S, occ: np.ndarray, V, seed: int, replica: int, sweep: int,
+                 a: int, beta: float) -> int:
+    """One trial in place on ``occ`` (uint8, C-contiguous).  Returns flags."""
+    assert occ.dtype == np.uint8 and occ.flags.c_contiguous
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    f = lib().or_single_trial(lattice, _ptr(_dims(dims)), K, S, _ptr(occ), _ptr(V), seed, replica,
+                              sweep, a, beta)
+    if f < 0:
+        raise ValueError("or_single_trial failed")
+    return int(f)
+
+
+class RunResult:
+    def __init__(self, stats, ties, n_ties, trace):
+        self.stats = stats
+        self.ties = ties
+        self.n_ties = n_ties
+        self.trace = trace
+
+
+def run(lattice, dims, K, S, cells, occ: np.ndarray, V, seed: int, betas, first_sweep: int = 0,
+        replica: int = 0, replay=None, tie_cap: int = 1024, trace: bool = False,
+        nthreads: int = 1) -> RunResult:
+    """Run len(betas) sweeps in place on ``occ``.
+
+    cells: list of three int arrays of link-cell edges (one per axis).
+    replay: structured array of TIE_DTYPE whose decisions override near-ties.
+    """
+    assert occ.dtype == np.uint8 and occ.flags.c_contiguous
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    betas = np.ascontiguousarray(np.asarray(betas, dtype=np.float64).reshape(-1))
+    ncell = np.array([len(c) for c in cells], np.int32)
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(c, np.int32) for c in cells]))
+    if replay is None:
+        replay = np.zeros(0, TIE_DTYPE)
+    replay = np.ascontiguousarray(replay, dtype=TIE_DTYPE)
+    stats = np.zeros(3, np.int64)
+    ties = np.zeros(max(tie_cap, 1), TIE_DTYPE)
+    n_ties = np.zeros(1, np.int32)
+    n_trials = int(np.prod(dims)) * (2 if lattice == BCC else 4) * len(betas)
+    tr = np.zeros(n_trials if trace else 0, TRACE_DTYPE)
+    rc = lib().or_run(lattice, _ptr(_dims(dims)), K, S, _ptr(ncell), _ptr(flat), _ptr(occ),
+                      _ptr(V), seed, replica, first_sweep, len(betas), _ptr(betas),
+                      _ptr(replay), len(replay), _ptr(stats), _ptr(ties), tie_cap,
+                      _ptr(n_ties), _ptr(tr) if trace else None, len(tr), nthreads)
+    if rc != 0:
+        raise ValueError("or_run failed (bad arguments)")
+    nt = int(n_ties[0])
+    return RunResult(stats, ties[:min(nt, tie_cap)].copy(), nt, tr if trace else None)
+
+
+def max_threads() -> int:
+    return int(lib().or_max_threads())
