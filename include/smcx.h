@@ -1,0 +1,234 @@
+/*
+ * smcx.h -- C ABI of libsmcx, link-cell parallel canonical swap Metropolis
+ * Monte Carlo with a multi-shell effective pair interaction (EPI) energy on
+ * BCC / FCC lattices, for AMD Instinct MI355X (gfx950).
+ *
+ * Method (paper: "Revealing Nanostructures in High-Entropy Alloys via
+ * Machine-Learning Accelerated Scalable Monte Carlo Simulation"):
+ *   - a sweep is n_A sequential mini-steps; a mini-step makes one trial in
+ *     every link cell, all of them independent (Results, "Performance of the
+ *     SMC-X algorithm", Fig. 1a/1c; Methods, "Implementation of SMC-GPU",
+ *     link-cell bullet; Fig. 7 caption);
+ *   - a trial swaps the species of a site with one of its nearest
+ *     neighbours and is accepted with probability min(1, exp(-beta dE))
+ *     (Supplementary, "Monte Carlo Simulation Algorithms");
+ *   - E = 1/2 sum_i sum_s sum_{d in D_s} V_s[sigma_i][sigma_{i+d}] (Methods,
+ *     "The EPI and qSRO model", Eq. Linear_EPI and Eq. Total_EPI), and dE of
+ *     a swap is twice the change of the two local energies (same section).
+ *
+ * Conventions fixed by this library (the paper leaves them open):
+ *   - positions in half lattice constants; BCC basis (0,0,0),(1,1,1); FCC
+ *     basis (0,0,0),(1,1,0),(1,0,1),(0,1,1); periodic boundaries;
+ *   - site index i = b + m*(x + Lx*(y + Ly*z)) for basis b (m = 2 BCC, 4 FCC)
+ *     and conventional cell (x, y, z); one uint8 species per site;
+ *   - shells D_s: lattice vectors of the s-th smallest length, sorted
+ *     lexicographically; D_1 fixes the partner direction k;
+ *   - per-axis partition into link cells; mini-step
+ *     tau = b + m*(o_x + M_x*(o_y + M_y*o_z)) ascending, M_a the largest cell
+ *     edge on axis a; a cell whose edge does not exceed an offset sits that
+ *     mini-step out;
+ *   - random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed,
+ *     counter = (site_lo, site_hi, sweep, replica); partner
+ *     k = floor(w0 * Z_1 / 2^32); u = ((w1 << 21) | (w2 >> 11)) * 2^-53;
+ *   - dE = sum_s sum_t (n_a - n_b)[s][t] * (V_s[q][t] - V_s[p][t]) in binary64,
+ *     s then t ascending, no fused multiply-add, where n_a counts the
+ *     neighbours of the active site a (species p) excluding the partner b
+ *     (species q) and n_b those of b excluding a; trials with p == q are
+ *     attempted but not accepted; accept if dE <= 0, else if u < exp(-beta dE);
+ *     |u - exp(-beta dE)| < 1e-12 is a near-tie and is logged.
+ *
+ * Memory and threading: the caller allocates every large device buffer
+ * (occupancy, workspace, counts, statistics, tie logs) and keeps it alive
+ * while the handle uses it.  The library never allocates device memory.
+ * Calls taking a stream are asynchronous on it unless they return host
+ * values, in which case they synchronise that stream before returning.
+ * A handle must not be used from two threads at once.  No C++ exception
+ * crosses this interface; every call returns an SMCX_* status.
+ */
+#ifndef SMCX_H
+#define SMCX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SMCX_VERSION 100
+
+/* status codes */
+#define SMCX_OK 0
+#define SMCX_E_INVALID_ARG (-1)   /* bad argument; smcx_last_error() says which */
+#define SMCX_E_UNSUPPORTED (-2)   /* valid request the library cannot serve */
+#define SMCX_E_NOT_READY (-3)     /* set_epi not called yet */
+#define SMCX_E_HIP (-4)           /* a HIP runtime call failed */
+#define SMCX_E_WORKSPACE (-5)     /* workspace too small */
+
+/* lattice kinds */
+#define SMCX_BCC 0
+#define SMCX_FCC 1
+
+/* sweep execution modes (all give the same trajectory) */
+#define SMCX_MODE_AUTO 0        /* persistent when R > 1 or the lattice is small, else stream */
+#define SMCX_MODE_STREAM 1      /* one launch per mini-step, batched over replicas */
+#define SMCX_MODE_PERSISTENT 2  /* one launch for all sweeps, one workgroup per replica */
+#define SMCX_MODE_PLAIN 3       /* one launch per replica per mini-step (baseline loop) */
+
+typedef struct smcx_lattice smcx_lattice;
+
+/* Near-tie record (24 bytes): the trial of `site` in `sweep` of `replica`
+ * came within 1e-12 of its acceptance threshold; `decision` is 1 when it was
+ * accepted. */
+typedef struct {
+    int32_t replica;
+    uint32_t sweep;
+    int64_t site;
+    int32_t decision;
+    int32_t pad;
+} smcx_tie;
+
+/* Problem description.  All pointers are host pointers, read during
+ * smcx_lattice_init only. */
+typedef struct {
+    int32_t lattice;       /* SMCX_BCC or SMCX_FCC */
+    int32_t n_species;     /* K, 2 .. 8 */
+    int32_t n_shells;      /* S, 1 .. 4 */
+    int32_t n_replicas;    /* R >= 1; replicas are stored back to back in occ */
+    const int32_t *dims;   /* [R][3] conventional cells per axis, each >= 2 */
+    const int32_t *ell;    /* [R] link-cell edge for the default partition rule
+                              (n = max(1, L / ell) cells per axis, edges L / n or
+                              L / n + 1, larger first), or NULL for 4.  Values
+                              below the minimum edge are raised to it. */
+    const int32_t *ncell;  /* [R][3] explicit partition: cells per axis, or NULL */
+    const int32_t *cells;  /* explicit partition: for each replica, the edges of
+                              the x cells, then y, then z, concatenated; each
+                              axis sums to its dimension and every edge is at
+                              least the minimum unless the axis has one cell */
+    int32_t tile[3];       /* link cells per workgroup tile along x, y, z
+                              (product <= 256), or {0,0,0} for the default */
+    uint32_t flags;        /* reserved, 0 */
+} smcx_desc;
+
+int smcx_version(void);
+
+/* Thread-local text of the last error (empty string when none). */
+const char *smcx_last_error(void);
+
+/* Smallest link-cell edge (conventional cells) for which the trials of one
+ * mini-step are independent: 2*ell > 2 + c_max, c_max the largest |component|
+ * (half-lattice units) over the first n_shells shells.  Returns the edge, or
+ * a negative status. */
+int smcx_min_cell_edge(int32_t lattice, int32_t n_shells);
+
+/* Device workspace (bytes) that smcx_lattice_init needs for this
+ * description.  It holds the per-replica metadata and tables and a padded
+ * working copy of the occupancy with a 2-cell periodic halo. */
+int smcx_workspace_size(const smcx_desc *desc, size_t *bytes);
+
+/* Create a handle.  occ_dev: device uint8 [sum_r N_r], replicas back to back
+ * in site-index order; ws_dev: device workspace of ws_bytes >=
+ * smcx_workspace_size, 256-byte aligned.  Uploads the tables on `stream`,
+ * checks on the device that every species is < K, and synchronises.
+ * The handle keeps both pointers; their memory must outlive it. */
+int smcx_lattice_init(smcx_lattice **out, const smcx_desc *desc, uint8_t *occ_dev, void *ws_dev,
+                      size_t ws_bytes, void *stream);
+
+int smcx_lattice_destroy(smcx_lattice *h);
+
+/* Partition actually used by replica r: ncell_out[3] cells per axis and the
+ * edges (x cells, then y, then z) in cells_out, which must hold
+ * Lx + Ly + Lz entries; *n_ministeps = M_x*M_y*M_z*m.  Feed these to a replay
+ * of the same trajectory. */
+int smcx_get_schedule(const smcx_lattice *h, int32_t replica, int32_t *ncell_out,
+                      int32_t *cells_out, int32_t *n_ministeps);
+
+/* Set the EPI tensor V (host, binary64, [S][K][K], eV).  V must be symmetric
+ * in (k, l) exactly.  Tables D[p][q][s][t] = V_s[q][t] - V_s[p][t] are uploaded
+ * on `stream`, which is synchronised. */
+int smcx_set_epi(smcx_lattice *h, const double *V, void *stream);
+
+/*
+ * Run n_sweeps sweeps on every replica, global sweep indices first_sweep ..
+ * first_sweep + n_sweeps - 1, mutating occ_dev in place.
+ *   beta_dev   device double [n_sweeps][R] inverse temperatures (1/eV)
+ *   stats_dev  device int64 [R][3], incremented by attempted, accepted and
+ *              near-tie counts
+ *   ties_dev   device smcx_tie [tie_cap] (may be NULL when tie_cap == 0)
+ *   tie_count_dev device int32 [1]: incremented once per near-tie; entries
+ *              past tie_cap are counted but not stored
+ *   mode       SMCX_MODE_*
+ * Asynchronous on `stream`.
+ */
+int smcx_sweep(smcx_lattice *h, int32_t n_sweeps, uint64_t seed, uint32_t first_sweep,
+               const double *beta_dev, int64_t *stats_dev, smcx_tie *ties_dev, int32_t tie_cap,
+               int32_t *tie_count_dev, int32_t mode, void *stream);
+
+/*
+ * Run only mini-steps [tau_begin, tau_end) of global sweep `sweep` (beta_dev:
+ * device double [R], the sweep's inverse temperatures; the other arguments as
+ * for smcx_sweep).  Replicas with fewer mini-steps run those they have.  A
+ * full sweep is tau_begin = 0, tau_end = the largest n_ministeps; splitting a
+ * sweep into ranges gives the same trajectory.  Used to checkpoint inside a
+ * sweep and to check single mini-steps against a sequential replay.
+ */
+int smcx_sweep_partial(smcx_lattice *h, uint32_t sweep, int32_t tau_begin, int32_t tau_end,
+                       uint64_t seed, const double *beta_dev, int64_t *stats_dev,
+                       smcx_tie *ties_dev, int32_t tie_cap, int32_t *tie_count_dev, int32_t mode,
+                       void *stream);
+
+/* Directed pair counts C[r][s][k][l] = #{(i, d in D_s) : sigma_i = k,
+ * sigma_{i+d} = l} of every replica into counts_dev (device int64
+ * [R][S][K][K], overwritten).  These are the per-shell pair numbers of the
+ * EPI features (Methods, "The EPI and qSRO model").  Asynchronous. */
+int smcx_pair_counts(smcx_lattice *h, int64_t *counts_dev, void *stream);
+
+/* Energies E[r] = 1/2 sum_{s,k,l} C[r][s][k][l] V_s[k][l] (binary64, s, k, l
+ * ascending) into E_host [R]; counts_dev as for smcx_pair_counts.
+ * Synchronises the stream.  (Eq. Total_EPI.) */
+int smcx_energy(smcx_lattice *h, int64_t *counts_dev, double *E_host, void *stream);
+
+/* Warren-Cowley short-range order alpha[r][s][k][l] =
+ * 1 - C N / (Z_s N_k N_l) into alpha_host [R][S][K][K] (host double).
+ * Returns SMCX_E_INVALID_ARG when a species is absent from a replica.
+ * Synchronises the stream. */
+int smcx_sro(smcx_lattice *h, int64_t *counts_dev, double *alpha_host, void *stream);
+
+/* Stateless batched pair counts for B configurations of one geometry:
+ * occ_batch_dev device uint8 [B][N] (N = m * dims[0]*dims[1]*dims[2]),
+ * counts_dev device int64 [B][S][K][K] (overwritten).  The gradient of
+ * E_b = 1/2 <C_b, V> with respect to V is C_b / 2.  Asynchronous. */
+int smcx_energy_backward(int32_t lattice, const int32_t *dims, int32_t n_species,
+                         int32_t n_shells, const uint8_t *occ_batch_dev, int32_t B,
+                         int64_t *counts_dev, void *stream);
+
+/*
+ * Temperature ladder as a replayable graph.  Captures, on `stream`, one
+ * persistent launch that runs n_sweeps sweeps on every replica with the
+ * fixed inverse temperatures beta_dev [R] (device double).  The first sweep
+ * index is read from *sweep_counter_dev (device uint32) when the graph runs
+ * and advanced by n_sweeps at its end, so every replay continues the chain.
+ * *graph_out receives an executable graph for smcx_graph_launch.  `stream`
+ * must be a created stream (the legacy default stream cannot be captured);
+ * nothing runs during the capture.
+ */
+int smcx_ladder_capture(smcx_lattice *h, int32_t n_sweeps, uint64_t seed, const double *beta_dev,
+                        uint32_t *sweep_counter_dev, int64_t *stats_dev, smcx_tie *ties_dev,
+                        int32_t tie_cap, int32_t *tie_count_dev, void *stream, void **graph_out);
+
+int smcx_graph_launch(void *graph, void *stream);
+
+int smcx_graph_destroy(void *graph);
+
+/* Kernel timing for measurement: while enabled, every mini-step and
+ * persistent sweep launch is bracketed with HIP events on its stream.
+ * smcx_timing_read synchronises, returns the summed kernel time (ms) and the
+ * number of timed launches since the last read, and resets both. */
+int smcx_timing_enable(smcx_lattice *h, int32_t enable);
+int smcx_timing_read(smcx_lattice *h, double *ms_out, int64_t *launches_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMCX_H */

@@ -1,0 +1,803 @@
+// C ABI of libsmcx (declared in include/smcx.h): argument checking, the
+// partition and launch plan, workspace layout, table upload and the sweep
+// drivers.  Everything that touches lattice sites runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "smcx.h"
+#include "smcx_internal.h"
+#include "smcx_launch.h"
+
+using namespace smcx;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define SMCX_HIP(call)                                                                              \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess) return fail(SMCX_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int lattice_m(int lattice) { return lattice == SMCX_BCC ? 2 : 4; }
+
+// Minimum link-cell edge: trials read within 1 + c_max half-units of their
+// site and write within 1; active sites of one mini-step are >= 2*ell apart
+// on some axis.  (Link cells larger than the interaction range, Methods,
+// link-cell bullet; LIZ / LIZ+ regions, Results and Fig. 1c.)
+int min_edge(int lattice, int S)
+{
+    const int c = max_component(kGeom[lattice], S);
+    int ell = 1;
+    while (!(2 * ell > 2 + c)) ++ell;
+    return ell;
+}
+
+struct Replica {
+    int L[3];
+    std::vector<int> edges[3];
+    std::vector<int> origin[3];  // nc + 1 entries
+    int M[3];
+    int nA;
+    int64_t N;
+    int64_t occ_off;
+    int ntile[3];
+    int64_t ntiles;
+    int prow, prows;
+    int64_t pad_off, pad_bytes;
+    int mult[kMaxShells][kMaxZ1];
+};
+
+struct Plan {
+    int lattice, K, S, R, m, Z1, sumZ;
+    int T[3];
+    std::vector<Replica> reps;
+    int LP, WY, WZ;
+    LdsLayout lds;
+    size_t off_reps, off_origins, off_tileoff, off_offP, off_offB, off_pd, off_D, off_misc, off_pad, total;
+    int n_origins;
+    int64_t total_sites, total_tiles;
+    int max_nA;
+};
+
+int make_plan(const smcx_desc* d, Plan& P)
+{
+    if (!d) return fail(SMCX_E_INVALID_ARG, "desc is NULL");
+    if (d->lattice != SMCX_BCC && d->lattice != SMCX_FCC) return fail(SMCX_E_INVALID_ARG, "lattice must be SMCX_BCC or SMCX_FCC");
+    if (d->n_species < 2 || d->n_species > kMaxK) return fail(SMCX_E_INVALID_ARG, "n_species must be in 2..8");
+    if (d->n_shells < 1 || d->n_shells > kMaxShells) return fail(SMCX_E_INVALID_ARG, "n_shells must be in 1..4");
+    if (d->n_replicas < 1) return fail(SMCX_E_INVALID_ARG, "n_replicas must be >= 1");
+    if (!d->dims) return fail(SMCX_E_INVALID_ARG, "dims is NULL");
+    if ((d->ncell == nullptr) != (d->cells == nullptr)) return fail(SMCX_E_INVALID_ARG, "ncell and cells must both be set or both NULL");
+    if (d->flags != 0) return fail(SMCX_E_INVALID_ARG, "flags must be 0");
+    P.lattice = d->lattice;
+    P.K = d->n_species;
+    P.S = d->n_shells;
+    P.R = d->n_replicas;
+    P.m = lattice_m(P.lattice);
+    const Geometry& G = kGeom[P.lattice];
+    P.Z1 = G.Z[0];
+    P.sumZ = sum_Z(G, P.S);
+    const int emin = min_edge(P.lattice, P.S);
+    if (d->tile[0] == 0 && d->tile[1] == 0 && d->tile[2] == 0) {
+        P.T[0] = 16; P.T[1] = 4; P.T[2] = 4;
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            if (d->tile[a] < 1) return fail(SMCX_E_INVALID_ARG, "tile edges must be >= 1");
+            P.T[a] = d->tile[a];
+        }
+        if ((int64_t)P.T[0] * P.T[1] * P.T[2] > kBlock) return fail(SMCX_E_INVALID_ARG, "tile holds more than 256 link cells");
+    }
+    P.reps.resize(P.R);
+    int64_t occ_off = 0;
+    size_t cells_pos = 0;
+    P.max_nA = 0;
+    for (int r = 0; r < P.R; ++r) {
+        Replica& R = P.reps[r];
+        for (int a = 0; a < 3; ++a) {
+            R.L[a] = d->dims[3 * r + a];
+            if (R.L[a] < 2) return fail(SMCX_E_INVALID_ARG, "every dimension must be >= 2 (replica " + std::to_string(r) + ")");
+            if (R.L[a] > (1 << 20)) return fail(SMCX_E_UNSUPPORTED, "dimension too large");
+        }
+        // no neighbour vector may map a site onto itself
+        for (int s = 0; s < P.S; ++s)
+            for (int n = 0; n < G.Z[s]; ++n) {
+                bool self = true;
+                for (int a = 0; a < 3; ++a) self &= (G.v[s][n][a] % (2 * R.L[a])) == 0;
+                if (self) return fail(SMCX_E_INVALID_ARG, "lattice too small: a site would be its own neighbour");
+            }
+        const int64_t ncell = (int64_t)R.L[0] * R.L[1] * R.L[2];
+        if (ncell > 0x7fffffffLL) return fail(SMCX_E_UNSUPPORTED, "more than 2^31 conventional cells in one replica");
+        R.N = ncell * P.m;
+        R.occ_off = occ_off;
+        occ_off += R.N;
+        for (int a = 0; a < 3; ++a) {
+            R.edges[a].clear();
+            if (d->cells) {
+                const int nc = d->ncell[3 * r + a];
+                if (nc < 1 || nc > R.L[a]) return fail(SMCX_E_INVALID_ARG, "bad ncell");
+                int sum = 0;
+                for (int j = 0; j < nc; ++j) {
+                    const int e = d->cells[cells_pos++];
+                    if (e < 1) return fail(SMCX_E_INVALID_ARG, "cell edges must be >= 1");
+                    R.edges[a].push_back(e);
+                    sum += e;
+                }
+                if (sum != R.L[a]) return fail(SMCX_E_INVALID_ARG, "cell edges do not sum to the dimension");
+            } else {
+                int ell = d->ell ? d->ell[r] : 4;
+                if (ell < 1) return fail(SMCX_E_INVALID_ARG, "ell must be >= 1");
+                ell = std::max(ell, emin);
+                const int n = std::max(1, R.L[a] / ell);
+                for (int j = 0; j < n; ++j) R.edges[a].push_back(R.L[a] / n + (j < R.L[a] % n ? 1 : 0));
+            }
+            if (R.edges[a].size() > 1)
+                for (int e : R.edges[a])
+                    if (e < emin)
+                        return fail(SMCX_E_INVALID_ARG, "link-cell edge " + std::to_string(e) + " below the minimum " +
+                                                            std::to_string(emin) + " for independent trials");
+            R.origin[a].assign(1, 0);
+            R.M[a] = 0;
+            for (int e : R.edges[a]) {
+                R.origin[a].push_back(R.origin[a].back() + e);
+                R.M[a] = std::max(R.M[a], e);
+            }
+            R.ntile[a] = ((int)R.edges[a].size() + P.T[a] - 1) / P.T[a];
+        }
+        R.nA = R.M[0] * R.M[1] * R.M[2] * P.m;
+        P.max_nA = std::max(P.max_nA, R.nA);
+        R.ntiles = (int64_t)R.ntile[0] * R.ntile[1] * R.ntile[2];
+        R.prow = (P.m * (R.L[0] + 2 * kHalo) + 15) & ~15;
+        R.prows = R.L[1] + 2 * kHalo;
+        R.pad_bytes = (int64_t)R.prow * R.prows * (R.L[2] + 2 * kHalo);
+        // partner images inside each shell: #{d in D_s : d == D_1[k] mod 2L}
+        for (int s = 0; s < kMaxShells; ++s)
+            for (int k = 0; k < kMaxZ1; ++k) R.mult[s][k] = 0;
+        for (int k = 0; k < P.Z1; ++k)
+            for (int s = 0; s < P.S; ++s)
+                for (int n = 0; n < G.Z[s]; ++n) {
+                    bool same = true;
+                    for (int a = 0; a < 3; ++a) same &= ((G.v[s][n][a] - G.v[0][k][a]) % (2 * R.L[a])) == 0;
+                    R.mult[s][k] += same ? 1 : 0;
+                }
+    }
+    if (d->cells) {
+        // nothing else to check: positions were consumed replica by replica
+    }
+    P.total_sites = occ_off;
+
+    // LDS window extents over every tile and offset (per axis independently)
+    int maxn[3] = {0, 0, 0};
+    int maxbytes = 0;
+    for (const Replica& R : P.reps)
+        for (int a = 0; a < 3; ++a) {
+            const int nc = (int)R.edges[a].size();
+            for (int ti = 0; ti < R.ntile[a]; ++ti) {
+                const int c0 = ti * P.T[a];
+                const int c1 = std::min(c0 + P.T[a], nc);
+                for (int o = 0; o < R.M[a]; ++o) {
+                    const int w0 = R.origin[a][c0] + o - kHalo;
+                    const int w1 = std::min(R.origin[a][c1 - 1] + o + kHalo + 1, R.L[a] + kHalo);
+                    if (w1 <= w0) continue;
+                    maxn[a] = std::max(maxn[a], w1 - w0);
+                    if (a == 0) {
+                        const int gx0 = (P.m * (w0 + kHalo)) & ~15;
+                        const int gx1 = (P.m * (w1 + kHalo) + 15) & ~15;
+                        maxbytes = std::max(maxbytes, gx1 - gx0);
+                    }
+                }
+            }
+        }
+    P.LP = maxbytes;
+    P.WY = maxn[1];
+    P.WZ = maxn[2];
+    if (P.LP > 16 * kBlock) return fail(SMCX_E_UNSUPPORTED, "tile window rows longer than 4096 bytes; use a smaller tile");
+    const int64_t win = (int64_t)P.LP * P.WY * P.WZ;
+    if (win > 160 * 1024) return fail(SMCX_E_UNSUPPORTED, "tile window does not fit in LDS; use a smaller tile");
+    P.lds = lds_layout(P.lattice, P.K, P.S, P.Z1, P.sumZ, (int)win);
+    if (P.lds.total > 160 * 1024) return fail(SMCX_E_UNSUPPORTED, "tile window and tables exceed 160 KiB of LDS");
+    const int64_t max_off = 2LL * P.LP * P.WY + 2LL * P.LP + 2 * P.m + 4;
+    if (max_off > 32767) return fail(SMCX_E_UNSUPPORTED, "LDS offsets exceed 16 bits; use a smaller tile");
+
+    // workspace layout
+    size_t o = 0;
+    P.off_reps = o; o = align256(o + sizeof(RepDev) * P.R);
+    P.n_origins = 0;
+    for (const Replica& R : P.reps)
+        for (int a = 0; a < 3; ++a) P.n_origins += (int)R.origin[a].size();
+    P.off_origins = o; o = align256(o + sizeof(int32_t) * P.n_origins);
+    P.off_tileoff = o; o = align256(o + sizeof(int64_t) * (P.R + 1));
+    P.off_offP = o; o = align256(o + sizeof(int16_t) * P.m * P.Z1 * P.sumZ);
+    P.off_offB = o; o = align256(o + sizeof(int32_t) * P.m * P.Z1);
+    P.off_pd = o; o = align256(o + 4 * P.m * P.Z1);
+    P.off_D = o; o = align256(o + sizeof(double) * P.K * P.K * P.S * P.K);
+    P.off_misc = o; o = align256(o + 256);
+    P.off_pad = o;
+    P.total_tiles = 0;
+    for (Replica& R : P.reps) {
+        R.pad_off = (int64_t)o;
+        o = align256(o + (size_t)R.pad_bytes);
+        P.total_tiles += R.ntiles;
+    }
+    P.total = o;
+    return SMCX_OK;
+}
+
+// LDS offset of the site at half-unit vector v from a basis-b site.
+int lds_offset(const Plan& P, int b, int vx, int vy, int vz)
+{
+    const Nb nb = nb_of(kGeom[P.lattice], b, vx, vy, vz);
+    return nb.dz * P.LP * P.WY + nb.dy * P.LP + P.m * nb.dx + (nb.bt - b);
+}
+
+}  // namespace
+
+struct smcx_lattice {
+    Plan P;
+    uint8_t* occ;
+    uint8_t* ws;
+    size_t ws_bytes;
+    bool epi_set = false;
+    std::vector<double> V;       // [S][K][K]
+    std::vector<double> Dhost;   // [K][K][S][K]
+    std::vector<int64_t> counts_host;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::vector<hipEvent_t> pool;
+    int64_t timed_launches = 0;
+};
+
+namespace {
+
+SweepArgs base_args(smcx_lattice* h)
+{
+    const Plan& P = h->P;
+    SweepArgs a{};
+    a.reps = (const RepDev*)(h->ws + P.off_reps);
+    a.origins = (const int32_t*)(h->ws + P.off_origins);
+    a.tile_off = (const int64_t*)(h->ws + P.off_tileoff);
+    a.offP = (const int16_t*)(h->ws + P.off_offP);
+    a.offB = (const int32_t*)(h->ws + P.off_offB);
+    a.pdisp = (const int8_t*)(h->ws + P.off_pd);
+    a.Dtab = (const double*)(h->ws + P.off_D);
+    a.ws = h->ws;
+    a.R = P.R;
+    a.K = P.K;
+    a.S = P.S;
+    a.Z1 = P.Z1;
+    a.sumZ = P.sumZ;
+    for (int i = 0; i < 3; ++i) a.T[i] = P.T[i];
+    a.LP = P.LP;
+    a.WY = P.WY;
+    a.WZ = P.WZ;
+    a.lds_d = P.lds.d_off;
+    a.lds_offp = P.lds.offp_off;
+    a.lds_offb = P.lds.offb_off;
+    a.lds_pd = P.lds.pd_off;
+    a.lds_mult = P.lds.mult_off;
+    a.lds_win = P.lds.win_off;
+    a.only_rep = -1;
+    a.sweep_counter = nullptr;
+    return a;
+}
+
+hipEvent_t take_event(smcx_lattice* h)
+{
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int timed_launch(smcx_lattice* h, bool persistent, dim3 grid, hipStream_t st, const SweepArgs& a)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->timing) {
+        e0 = take_event(h);
+        e1 = take_event(h);
+        if (!e0 || !e1) return fail(SMCX_E_HIP, "hipEventCreate failed");
+        SMCX_HIP(hipEventRecord(e0, st));
+    }
+    SMCX_HIP(launch_sweep(h->P.lattice, h->P.K, persistent, grid, h->P.lds.total, st, a));
+    if (h->timing) {
+        SMCX_HIP(hipEventRecord(e1, st));
+        h->pending.emplace_back(e0, e1);
+        ++h->timed_launches;
+    }
+    return SMCX_OK;
+}
+
+int pack_all(smcx_lattice* h, bool unpack, hipStream_t st)
+{
+    const Plan& P = h->P;
+    for (int r = 0; r < P.R; ++r) {
+        const int64_t ncell = P.reps[r].N / P.m;
+        SMCX_HIP(launch_pack(P.lattice, unpack, h->occ, h->ws, (const RepDev*)(h->ws + P.off_reps), r, ncell, st));
+    }
+    return SMCX_OK;
+}
+
+int check_handle(const smcx_lattice* h)
+{
+    if (!h) return fail(SMCX_E_INVALID_ARG, "handle is NULL");
+    return SMCX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int smcx_version(void) { return SMCX_VERSION; }
+
+const char* smcx_last_error(void) { return g_err.c_str(); }
+
+int smcx_min_cell_edge(int32_t lattice, int32_t n_shells)
+{
+    if (lattice != SMCX_BCC && lattice != SMCX_FCC) return fail(SMCX_E_INVALID_ARG, "bad lattice");
+    if (n_shells < 1 || n_shells > kMaxShells) return fail(SMCX_E_INVALID_ARG, "bad n_shells");
+    return min_edge(lattice, n_shells);
+}
+
+int smcx_workspace_size(const smcx_desc* desc, size_t* bytes)
+{
+    if (!bytes) return fail(SMCX_E_INVALID_ARG, "bytes is NULL");
+    Plan P;
+    const int rc = make_plan(desc, P);
+    if (rc != SMCX_OK) return rc;
+    *bytes = P.total;
+    return SMCX_OK;
+}
+
+int smcx_lattice_init(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_dev, void* ws_dev, size_t ws_bytes,
+                      void* stream)
+{
+    if (!out) return fail(SMCX_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!occ_dev || !ws_dev) return fail(SMCX_E_INVALID_ARG, "occ_dev and ws_dev must be device pointers");
+    if (((uintptr_t)ws_dev & 255) != 0) return fail(SMCX_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    smcx_lattice* h = new (std::nothrow) smcx_lattice();
+    if (!h) return fail(SMCX_E_INVALID_ARG, "out of host memory");
+    int rc = make_plan(desc, h->P);
+    if (rc != SMCX_OK) {
+        delete h;
+        return rc;
+    }
+    const Plan& P = h->P;
+    if (ws_bytes < P.total) {
+        delete h;
+        return fail(SMCX_E_WORKSPACE, "workspace too small: need " + std::to_string(P.total) + " bytes");
+    }
+    h->occ = occ_dev;
+    h->ws = (uint8_t*)ws_dev;
+    h->ws_bytes = ws_bytes;
+    hipStream_t st = (hipStream_t)stream;
+
+    // host images of the device tables
+    std::vector<RepDev> reps(P.R);
+    std::vector<int32_t> origins;
+    std::vector<int64_t> tile_off(P.R + 1, 0);
+    for (int r = 0; r < P.R; ++r) {
+        const Replica& R = P.reps[r];
+        RepDev& D = reps[r];
+        std::memset(&D, 0, sizeof(D));
+        for (int a = 0; a < 3; ++a) {
+            D.L[a] = R.L[a];
+            D.nc[a] = (int)R.edges[a].size();
+            D.M[a] = R.M[a];
+            D.ntile[a] = R.ntile[a];
+        }
+        D.nA = R.nA;
+        D.cs_off = (int)origins.size();
+        for (int a = 0; a < 3; ++a) origins.insert(origins.end(), R.origin[a].begin(), R.origin[a].end());
+        D.prow = R.prow;
+        D.prows = R.prows;
+        D.pad_off = R.pad_off;
+        D.occ_off = R.occ_off;
+        D.N = R.N;
+        D.ntiles = R.ntiles;
+        for (int s = 0; s < kMaxShells; ++s)
+            for (int k = 0; k < kMaxZ1; ++k) D.mult[s][k] = (uint8_t)R.mult[s][k];
+        tile_off[r + 1] = tile_off[r] + R.ntiles;
+    }
+    const Geometry& G = kGeom[P.lattice];
+    std::vector<int16_t> offP((size_t)P.m * P.Z1 * P.sumZ);
+    std::vector<int32_t> offB((size_t)P.m * P.Z1);
+    std::vector<int8_t> pd((size_t)4 * P.m * P.Z1);
+    for (int b = 0; b < P.m; ++b)
+        for (int k = 0; k < P.Z1; ++k) {
+            const int* d1 = G.v[0][k];
+            offB[b * P.Z1 + k] = lds_offset(P, b, d1[0], d1[1], d1[2]);
+            const Nb nb = nb_of(G, b, d1[0], d1[1], d1[2]);
+            int8_t* q = &pd[(b * P.Z1 + k) * 4];
+            q[0] = (int8_t)nb.dx; q[1] = (int8_t)nb.dy; q[2] = (int8_t)nb.dz; q[3] = (int8_t)nb.bt;
+            int j = 0;
+            for (int s = 0; s < P.S; ++s)
+                for (int n = 0; n < G.Z[s]; ++n, ++j)
+                    offP[(b * P.Z1 + k) * P.sumZ + j] =
+                        (int16_t)lds_offset(P, b, d1[0] + G.v[s][n][0], d1[1] + G.v[s][n][1], d1[2] + G.v[s][n][2]);
+        }
+    SMCX_HIP(hipMemcpyAsync(h->ws + P.off_reps, reps.data(), sizeof(RepDev) * P.R, hipMemcpyHostToDevice, st));
+    SMCX_HIP(hipMemcpyAsync(h->ws + P.off_origins, origins.data(), sizeof(int32_t) * origins.size(), hipMemcpyHostToDevice, st));
+    SMCX_HIP(hipMemcpyAsync(h->ws + P.off_tileoff, tile_off.data(), sizeof(int64_t) * tile_off.size(), hipMemcpyHostToDevice, st));
+    SMCX_HIP(hipMemcpyAsync(h->ws + P.off_offP, offP.data(), sizeof(int16_t) * offP.size(), hipMemcpyHostToDevice, st));
+    SMCX_HIP(hipMemcpyAsync(h->ws + P.off_offB, offB.data(), sizeof(int32_t) * offB.size(), hipMemcpyHostToDevice, st));
+    SMCX_HIP(hipMemcpyAsync(h->ws + P.off_pd, pd.data(), pd.size(), hipMemcpyHostToDevice, st));
+    int32_t* bad = (int32_t*)(h->ws + P.off_misc);
+    SMCX_HIP(launch_fill_i32(bad, 1, 0, st));
+    SMCX_HIP(launch_validate(occ_dev, P.total_sites, P.K, bad, st));
+    int32_t bad_h = 0;
+    SMCX_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SMCX_HIP(hipStreamSynchronize(st));
+    if (bad_h) {
+        delete h;
+        return fail(SMCX_E_INVALID_ARG, "occupancy holds a species >= n_species");
+    }
+    SMCX_HIP(set_sweep_lds_limit(P.lattice, P.K, P.lds.total));
+    *out = h;
+    g_err.clear();
+    return SMCX_OK;
+}
+
+int smcx_lattice_destroy(smcx_lattice* h)
+{
+    if (!h) return SMCX_OK;
+    for (auto& pr : h->pending) {
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+    }
+    for (hipEvent_t e : h->pool) hipEventDestroy(e);
+    delete h;
+    return SMCX_OK;
+}
+
+int smcx_get_schedule(const smcx_lattice* h, int32_t replica, int32_t* ncell_out, int32_t* cells_out,
+                      int32_t* n_ministeps)
+{
+    if (int rc = check_handle(h)) return rc;
+    if (replica < 0 || replica >= h->P.R) return fail(SMCX_E_INVALID_ARG, "replica out of range");
+    const Replica& R = h->P.reps[replica];
+    int pos = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (ncell_out) ncell_out[a] = (int32_t)R.edges[a].size();
+        for (int e : R.edges[a]) {
+            if (cells_out) cells_out[pos] = e;
+            ++pos;
+        }
+    }
+    if (n_ministeps) *n_ministeps = R.nA;
+    return SMCX_OK;
+}
+
+int smcx_set_epi(smcx_lattice* h, const double* V, void* stream)
+{
+    if (int rc = check_handle(h)) return rc;
+    if (!V) return fail(SMCX_E_INVALID_ARG, "V is NULL");
+    const Plan& P = h->P;
+    const int K = P.K, S = P.S;
+    for (int s = 0; s < S; ++s)
+        for (int k = 0; k < K; ++k)
+            for (int l = 0; l < K; ++l) {
+                const double a = V[(s * K + k) * K + l], b = V[(s * K + l) * K + k];
+                if (!(a == b)) return fail(SMCX_E_INVALID_ARG, "V must be symmetric in its species indices (and finite)");
+            }
+    h->V.assign(V, V + (size_t)S * K * K);
+    h->Dhost.resize((size_t)K * K * S * K);
+    for (int p = 0; p < K; ++p)
+        for (int q = 0; q < K; ++q)
+            for (int s = 0; s < S; ++s)
+                for (int t = 0; t < K; ++t)
+                    h->Dhost[((p * K + q) * S + s) * K + t] = V[(s * K + q) * K + t] - V[(s * K + p) * K + t];
+    hipStream_t st = (hipStream_t)stream;
+    SMCX_HIP(hipMemcpyAsync(h->ws + P.off_D, h->Dhost.data(), sizeof(double) * h->Dhost.size(), hipMemcpyHostToDevice, st));
+    SMCX_HIP(hipStreamSynchronize(st));
+    h->epi_set = true;
+    return SMCX_OK;
+}
+
+static int check_sweep_args(smcx_lattice* h, const double* beta_dev, int64_t* stats_dev, smcx_tie* ties_dev,
+                            int32_t tie_cap, int32_t* tie_count_dev, int32_t mode)
+{
+    if (int rc = check_handle(h)) return rc;
+    if (!h->epi_set) return fail(SMCX_E_NOT_READY, "smcx_set_epi has not been called");
+    if (!beta_dev || !stats_dev || !tie_count_dev) return fail(SMCX_E_INVALID_ARG, "beta, stats and tie_count are required");
+    if (tie_cap < 0 || (tie_cap > 0 && !ties_dev)) return fail(SMCX_E_INVALID_ARG, "ties_dev required when tie_cap > 0");
+    if (mode < SMCX_MODE_AUTO || mode > SMCX_MODE_PLAIN) return fail(SMCX_E_INVALID_ARG, "bad mode");
+    return SMCX_OK;
+}
+
+// Sweeps first_sweep .. first_sweep + n_sweeps - 1, mini-steps [tau_begin,
+// tau_end) of each; beta_dev row js (R entries) belongs to sweep js.
+static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t first_sweep, int tau_begin,
+                      int tau_end, const double* beta_dev, int64_t* stats_dev, smcx_tie* ties_dev, int32_t tie_cap,
+                      int32_t* tie_count_dev, int32_t mode, hipStream_t st)
+{
+    const Plan& P = h->P;
+    if (mode == SMCX_MODE_AUTO)
+        mode = (P.R > 1 || P.total_sites <= (1 << 16)) ? SMCX_MODE_PERSISTENT : SMCX_MODE_STREAM;
+    if (int rc = pack_all(h, false, st)) return rc;
+    SweepArgs a = base_args(h);
+    a.seed = seed;
+    a.stats = stats_dev;
+    a.ties = ties_dev;
+    a.tie_cap = tie_cap;
+    a.tie_count = tie_count_dev;
+    a.n_sweeps = n_sweeps;
+    a.tau_begin = tau_begin;
+    a.tau_end = tau_end;
+    if (mode == SMCX_MODE_PERSISTENT) {
+        a.first_sweep = first_sweep;
+        a.beta = beta_dev;
+        a.beta_stride = P.R;
+        if (int rc = timed_launch(h, true, dim3(P.R), st, a)) return rc;
+    } else if (mode == SMCX_MODE_STREAM) {
+        a.xcd_per = (int32_t)((P.total_tiles + 7) / 8);
+        const dim3 grid((unsigned)(8 * (int64_t)a.xcd_per));
+        for (int js = 0; js < n_sweeps; ++js) {
+            a.first_sweep = first_sweep + (uint32_t)js;
+            a.beta = beta_dev + (int64_t)js * P.R;
+            for (int g = tau_begin; g < std::min(tau_end, P.max_nA); ++g) {
+                a.g = g;
+                if (int rc = timed_launch(h, false, grid, st, a)) return rc;
+            }
+        }
+    } else {
+        for (int js = 0; js < n_sweeps; ++js) {
+            a.first_sweep = first_sweep + (uint32_t)js;
+            a.beta = beta_dev + (int64_t)js * P.R;
+            for (int r = 0; r < P.R; ++r) {
+                a.only_rep = r;
+                a.xcd_per = (int32_t)((P.reps[r].ntiles + 7) / 8);
+                const dim3 grid((unsigned)(8 * (int64_t)a.xcd_per));
+                for (int g = tau_begin; g < std::min(tau_end, P.reps[r].nA); ++g) {
+                    a.g = g;
+                    if (int rc = timed_launch(h, false, grid, st, a)) return rc;
+                }
+            }
+        }
+    }
+    return pack_all(h, true, st);
+}
+
+int smcx_sweep(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t first_sweep, const double* beta_dev,
+               int64_t* stats_dev, smcx_tie* ties_dev, int32_t tie_cap, int32_t* tie_count_dev, int32_t mode,
+               void* stream)
+{
+    if (n_sweeps < 0) return fail(SMCX_E_INVALID_ARG, "n_sweeps must be >= 0");
+    if (int rc = check_sweep_args(h, beta_dev, stats_dev, ties_dev, tie_cap, tie_count_dev, mode)) return rc;
+    if (n_sweeps == 0) return SMCX_OK;
+    return run_sweeps(h, n_sweeps, seed, first_sweep, 0, h->P.max_nA, beta_dev, stats_dev, ties_dev, tie_cap,
+                      tie_count_dev, mode, (hipStream_t)stream);
+}
+
+int smcx_sweep_partial(smcx_lattice* h, uint32_t sweep, int32_t tau_begin, int32_t tau_end, uint64_t seed,
+                       const double* beta_dev, int64_t* stats_dev, smcx_tie* ties_dev, int32_t tie_cap,
+                       int32_t* tie_count_dev, int32_t mode, void* stream)
+{
+    if (int rc = check_sweep_args(h, beta_dev, stats_dev, ties_dev, tie_cap, tie_count_dev, mode)) return rc;
+    if (tau_begin < 0 || tau_end < tau_begin || tau_end > h->P.max_nA)
+        return fail(SMCX_E_INVALID_ARG, "mini-step range out of bounds");
+    if (tau_end == tau_begin) return SMCX_OK;
+    return run_sweeps(h, 1, seed, sweep, tau_begin, tau_end, beta_dev, stats_dev, ties_dev, tie_cap, tie_count_dev,
+                      mode, (hipStream_t)stream);
+}
+
+int smcx_pair_counts(smcx_lattice* h, int64_t* counts_dev, void* stream)
+{
+    if (int rc = check_handle(h)) return rc;
+    if (!counts_dev) return fail(SMCX_E_INVALID_ARG, "counts_dev is NULL");
+    const Plan& P = h->P;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t per = (int64_t)P.S * P.K * P.K;
+    SMCX_HIP(launch_fill_i64(counts_dev, per * P.R, 0, st));
+    for (int r = 0; r < P.R; ++r) {
+        const Replica& R = P.reps[r];
+        SMCX_HIP(launch_pair_counts(P.lattice, P.K, P.S, h->occ + R.occ_off, R.N, R.L, 1, counts_dev + per * r, st));
+    }
+    return SMCX_OK;
+}
+
+static int fetch_counts(smcx_lattice* h, int64_t* counts_dev, hipStream_t st)
+{
+    const Plan& P = h->P;
+    if (int rc = smcx_pair_counts(h, counts_dev, st)) return rc;
+    h->counts_host.resize((size_t)P.R * P.S * P.K * P.K);
+    SMCX_HIP(hipMemcpyAsync(h->counts_host.data(), counts_dev, sizeof(int64_t) * h->counts_host.size(),
+                            hipMemcpyDeviceToHost, st));
+    SMCX_HIP(hipStreamSynchronize(st));
+    return SMCX_OK;
+}
+
+int smcx_energy(smcx_lattice* h, int64_t* counts_dev, double* E_host, void* stream)
+{
+    if (int rc = check_handle(h)) return rc;
+    if (!h->epi_set) return fail(SMCX_E_NOT_READY, "smcx_set_epi has not been called");
+    if (!E_host) return fail(SMCX_E_INVALID_ARG, "E_host is NULL");
+    if (int rc = fetch_counts(h, counts_dev, (hipStream_t)stream)) return rc;
+    const Plan& P = h->P;
+    const int K = P.K, S = P.S;
+    for (int r = 0; r < P.R; ++r) {
+        const int64_t* C = h->counts_host.data() + (size_t)r * S * K * K;
+        double acc = 0.0;
+        for (int s = 0; s < S; ++s)
+            for (int k = 0; k < K; ++k)
+                for (int l = 0; l < K; ++l) {
+                    const size_t i = ((size_t)s * K + k) * K + l;
+                    acc = acc + (double)C[i] * h->V[i];
+                }
+        E_host[r] = 0.5 * acc;
+    }
+    return SMCX_OK;
+}
+
+int smcx_sro(smcx_lattice* h, int64_t* counts_dev, double* alpha_host, void* stream)
+{
+    if (int rc = check_handle(h)) return rc;
+    if (!alpha_host) return fail(SMCX_E_INVALID_ARG, "alpha_host is NULL");
+    if (int rc = fetch_counts(h, counts_dev, (hipStream_t)stream)) return rc;
+    const Plan& P = h->P;
+    const int K = P.K, S = P.S;
+    const Geometry& G = kGeom[P.lattice];
+    for (int r = 0; r < P.R; ++r) {
+        const int64_t* C = h->counts_host.data() + (size_t)r * S * K * K;
+        int64_t Nk[kMaxK];
+        int64_t N = 0;
+        for (int k = 0; k < K; ++k) {
+            int64_t row = 0;
+            for (int l = 0; l < K; ++l) row += C[k * K + l];
+            Nk[k] = row / G.Z[0];
+            if (Nk[k] == 0) return fail(SMCX_E_INVALID_ARG, "species " + std::to_string(k) + " absent from replica " + std::to_string(r));
+            N += Nk[k];
+        }
+        double* al = alpha_host + (size_t)r * S * K * K;
+        for (int s = 0; s < S; ++s)
+            for (int k = 0; k < K; ++k)
+                for (int l = 0; l < K; ++l) {
+                    const size_t i = ((size_t)s * K + k) * K + l;
+                    al[i] = 1.0 - ((double)C[i] * (double)N) / (((double)G.Z[s] * (double)Nk[k]) * (double)Nk[l]);
+                }
+    }
+    return SMCX_OK;
+}
+
+int smcx_energy_backward(int32_t lattice, const int32_t* dims, int32_t n_species, int32_t n_shells,
+                         const uint8_t* occ_batch_dev, int32_t B, int64_t* counts_dev, void* stream)
+{
+    if (lattice != SMCX_BCC && lattice != SMCX_FCC) return fail(SMCX_E_INVALID_ARG, "bad lattice");
+    if (n_species < 2 || n_species > kMaxK) return fail(SMCX_E_INVALID_ARG, "n_species must be in 2..8");
+    if (n_shells < 1 || n_shells > kMaxShells) return fail(SMCX_E_INVALID_ARG, "n_shells must be in 1..4");
+    if (!dims || B < 0) return fail(SMCX_E_INVALID_ARG, "bad dims or B");
+    if (B == 0) return SMCX_OK;
+    if (!occ_batch_dev || !counts_dev) return fail(SMCX_E_INVALID_ARG, "NULL device pointer");
+    const Geometry& G = kGeom[lattice];
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 2) return fail(SMCX_E_INVALID_ARG, "every dimension must be >= 2");
+    for (int s = 0; s < n_shells; ++s)
+        for (int n = 0; n < G.Z[s]; ++n) {
+            bool self = true;
+            for (int a = 0; a < 3; ++a) self &= (G.v[s][n][a] % (2 * dims[a])) == 0;
+            if (self) return fail(SMCX_E_INVALID_ARG, "lattice too small: a site would be its own neighbour");
+        }
+    const int64_t N = (int64_t)lattice_m(lattice) * dims[0] * dims[1] * dims[2];
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t per = (int64_t)n_shells * n_species * n_species;
+    SMCX_HIP(launch_fill_i64(counts_dev, per * B, 0, st));
+    for (int32_t b0 = 0; b0 < B; b0 += 65535) {
+        const int nb = std::min<int32_t>(65535, B - b0);
+        SMCX_HIP(launch_pair_counts(lattice, n_species, n_shells, occ_batch_dev + (int64_t)b0 * N, N, dims, nb,
+                                    counts_dev + per * b0, st));
+    }
+    return SMCX_OK;
+}
+
+int smcx_ladder_capture(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, const double* beta_dev,
+                        uint32_t* sweep_counter_dev, int64_t* stats_dev, smcx_tie* ties_dev, int32_t tie_cap,
+                        int32_t* tie_count_dev, void* stream, void** graph_out)
+{
+    if (int rc = check_handle(h)) return rc;
+    if (!graph_out) return fail(SMCX_E_INVALID_ARG, "graph_out is NULL");
+    *graph_out = nullptr;
+    if (!h->epi_set) return fail(SMCX_E_NOT_READY, "smcx_set_epi has not been called");
+    if (n_sweeps < 1) return fail(SMCX_E_INVALID_ARG, "n_sweeps must be >= 1");
+    if (!beta_dev || !sweep_counter_dev || !stats_dev || !tie_count_dev)
+        return fail(SMCX_E_INVALID_ARG, "beta, sweep counter, stats and tie_count are required");
+    if (tie_cap < 0 || (tie_cap > 0 && !ties_dev)) return fail(SMCX_E_INVALID_ARG, "ties_dev required when tie_cap > 0");
+    if (h->timing) return fail(SMCX_E_INVALID_ARG, "disable timing before capturing a graph");
+    if (stream == nullptr) return fail(SMCX_E_INVALID_ARG, "the legacy default stream cannot be captured; pass a created stream");
+    const Plan& P = h->P;
+    hipStream_t st = (hipStream_t)stream;
+    SMCX_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    SweepArgs a = base_args(h);
+    a.seed = seed;
+    a.stats = stats_dev;
+    a.ties = ties_dev;
+    a.tie_cap = tie_cap;
+    a.tie_count = tie_count_dev;
+    a.n_sweeps = n_sweeps;
+    a.first_sweep = 0;
+    a.sweep_counter = sweep_counter_dev;
+    a.beta = beta_dev;
+    a.beta_stride = 0;
+    a.tau_begin = 0;
+    a.tau_end = P.max_nA;
+    int rc = pack_all(h, false, st);
+    hipError_t e = hipSuccess;
+    if (rc == SMCX_OK) e = launch_sweep(P.lattice, P.K, true, dim3(P.R), P.lds.total, st, a);
+    if (rc == SMCX_OK && e == hipSuccess) e = launch_advance_counter(sweep_counter_dev, (uint32_t)n_sweeps, st);
+    if (rc == SMCX_OK && e == hipSuccess) rc = pack_all(h, true, st);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(st, &graph);
+    if (rc != SMCX_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        return fail(SMCX_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(SMCX_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    *graph_out = (void*)exec;
+    return SMCX_OK;
+}
+
+int smcx_graph_launch(void* graph, void* stream)
+{
+    if (!graph) return fail(SMCX_E_INVALID_ARG, "graph is NULL");
+    SMCX_HIP(hipGraphLaunch((hipGraphExec_t)graph, (hipStream_t)stream));
+    return SMCX_OK;
+}
+
+int smcx_graph_destroy(void* graph)
+{
+    if (!graph) return SMCX_OK;
+    SMCX_HIP(hipGraphExecDestroy((hipGraphExec_t)graph));
+    return SMCX_OK;
+}
+
+int smcx_timing_enable(smcx_lattice* h, int32_t enable)
+{
+    if (int rc = check_handle(h)) return rc;
+    h->timing = enable != 0;
+    return SMCX_OK;
+}
+
+int smcx_timing_read(smcx_lattice* h, double* ms_out, int64_t* launches_out)
+{
+    if (int rc = check_handle(h)) return rc;
+    double total = 0.0;
+    if (!h->pending.empty()) SMCX_HIP(hipEventSynchronize(h->pending.back().second));
+    for (auto& pr : h->pending) {
+        float ms = 0.f;
+        SMCX_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+        total += ms;
+        h->pool.push_back(pr.first);
+        h->pool.push_back(pr.second);
+    }
+    h->pending.clear();
+    if (ms_out) *ms_out = total;
+    if (launches_out) *launches_out = h->timed_launches;
+    h->timed_launches = 0;
+    return SMCX_OK;
+}
+
+}  // extern "C"

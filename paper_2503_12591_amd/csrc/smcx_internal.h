@@ -1,0 +1,202 @@
+// Internal definitions of libsmcx shared by the host driver and the gfx950
+// kernels: lattice geometry (compile-time shell tables), per-replica metadata
+// and kernel argument blocks.
+#pragma once
+
+#include <stdint.h>
+
+#include "smcx.h"
+
+namespace smcx {
+
+// Halo, in conventional cells, of the padded occupancy copy and of every tile
+// window.  A pair-model trial reads within 1 + c_max <= 4 half-units of its
+// site (c_max <= 3 for the first four BCC / FCC shells), which lies within
+// two conventional cells on every axis.
+constexpr int kHalo = 2;
+constexpr int kMaxShells = 4;
+constexpr int kMaxZ = 24;
+constexpr int kMaxK = 8;
+constexpr int kMaxZ1 = 12;
+constexpr int kMaxSumZ = 54;
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// Geometry.  Positions are in half lattice constants.  Coordination shells are
+// the lattice vectors of the s-th smallest non-zero length, in lexicographic
+// (dx, dy, dz) order; the first shell lists the swap partners (Methods,
+// "Search neighbors": neighbours are found from a list of relative
+// positions).  Built at compile time by enumerating a small box.
+// ---------------------------------------------------------------------------
+struct Geometry {
+    int m;
+    int basis[4][3];
+    int nshell;
+    int r2[kMaxShells];
+    int Z[kMaxShells];
+    int v[kMaxShells][kMaxZ][3];
+};
+
+constexpr int parity(int a) { return a & 1; }  // two's complement: also right for a < 0
+
+constexpr int basis_of_parity(const Geometry& g, int px, int py, int pz)
+{
+    for (int b = 0; b < g.m; ++b)
+        if (g.basis[b][0] == px && g.basis[b][1] == py && g.basis[b][2] == pz) return b;
+    return -1;
+}
+
+constexpr Geometry make_geometry(int lattice)
+{
+    Geometry g{};
+    if (lattice == SMCX_BCC) {
+        g.m = 2;
+        g.basis[1][0] = g.basis[1][1] = g.basis[1][2] = 1;
+    } else {
+        g.m = 4;
+        g.basis[1][0] = 1; g.basis[1][1] = 1;
+        g.basis[2][0] = 1; g.basis[2][2] = 1;
+        g.basis[3][1] = 1; g.basis[3][2] = 1;
+    }
+    g.nshell = 0;
+    for (int r2 = 1; r2 < 32 && g.nshell < kMaxShells; ++r2) {
+        int n = 0;
+        for (int x = -3; x <= 3; ++x)
+            for (int y = -3; y <= 3; ++y)
+                for (int z = -3; z <= 3; ++z) {
+                    if (x * x + y * y + z * z != r2) continue;
+                    if (basis_of_parity(g, parity(x), parity(y), parity(z)) < 0) continue;
+                    g.v[g.nshell][n][0] = x;
+                    g.v[g.nshell][n][1] = y;
+                    g.v[g.nshell][n][2] = z;
+                    ++n;
+                }
+        if (n > 0) {
+            g.r2[g.nshell] = r2;
+            g.Z[g.nshell] = n;
+            ++g.nshell;
+        }
+    }
+    return g;
+}
+
+constexpr Geometry kGeom[2] = {make_geometry(SMCX_BCC), make_geometry(SMCX_FCC)};
+
+// Neighbour of a basis-b site by half-unit vector (vx, vy, vz): the target
+// basis bt and the displacement (dx, dy, dz) of its conventional cell.
+struct Nb {
+    int dx, dy, dz, bt;
+};
+
+constexpr Nb nb_of(const Geometry& g, int b, int vx, int vy, int vz)
+{
+    const int hx = g.basis[b][0] + vx, hy = g.basis[b][1] + vy, hz = g.basis[b][2] + vz;
+    const int bt = basis_of_parity(g, parity(hx), parity(hy), parity(hz));
+    Nb n{};
+    n.bt = bt;
+    n.dx = (hx - g.basis[bt][0]) / 2;  // exact: the difference is even
+    n.dy = (hy - g.basis[bt][1]) / 2;
+    n.dz = (hz - g.basis[bt][2]) / 2;
+    return n;
+}
+
+constexpr int max_component(const Geometry& g, int S)
+{
+    int c = 0;
+    for (int s = 0; s < S; ++s)
+        for (int n = 0; n < g.Z[s]; ++n)
+            for (int a = 0; a < 3; ++a) {
+                const int v = g.v[s][n][a] < 0 ? -g.v[s][n][a] : g.v[s][n][a];
+                if (v > c) c = v;
+            }
+    return c;
+}
+
+constexpr int sum_Z(const Geometry& g, int S)
+{
+    int t = 0;
+    for (int s = 0; s < S; ++s) t += g.Z[s];
+    return t;
+}
+
+static_assert(kGeom[0].Z[0] == 8 && kGeom[0].Z[1] == 6 && kGeom[0].Z[2] == 12 && kGeom[0].Z[3] == 24,
+              "BCC coordination numbers");
+static_assert(kGeom[1].Z[0] == 12 && kGeom[1].Z[1] == 6 && kGeom[1].Z[2] == 24 && kGeom[1].Z[3] == 12,
+              "FCC coordination numbers");
+static_assert(max_component(kGeom[0], 4) == 3 && max_component(kGeom[1], 4) == 2, "shell reach");
+
+// ---------------------------------------------------------------------------
+// Per-replica metadata, stored in the workspace.
+// Padded copy: conventional cell x in [-kHalo, L + kHalo) on every axis; byte
+// of site (x, y, z, b) = pad_off + ((z + H) * prows + (y + H)) * prow
+//                        + m * (x + H) + b.
+// ---------------------------------------------------------------------------
+struct RepDev {
+    int32_t L[3];        // conventional cells per axis
+    int32_t nc[3];       // link cells per axis
+    int32_t M[3];        // largest link-cell edge per axis
+    int32_t nA;          // mini-steps per sweep
+    int32_t ntile[3];    // tiles per axis
+    int32_t cs_off;      // cell-origin table offset (x: nc0+1 entries, then y, then z)
+    int32_t prow;        // padded row pitch (bytes, multiple of 16)
+    int32_t prows;       // rows per padded plane (L1 + 2H)
+    int32_t pad0;
+    int64_t pad_off;     // byte offset of the padded copy in the workspace
+    int64_t occ_off;     // first site of this replica in the occupancy array
+    int64_t N;           // sites
+    int64_t ntiles;      // tiles per mini-step
+    uint8_t mult[kMaxShells][kMaxZ1];  // images of the partner inside each shell
+};
+
+// Arguments of the sweep kernels (passed by value).
+struct SweepArgs {
+    const RepDev* reps;
+    const int32_t* origins;
+    const int64_t* tile_off;   // [R + 1] prefix sums of tiles per replica
+    const int16_t* offP;       // [m][Z1][sumZ] partner-neighbour offsets relative to the active site
+    const int32_t* offB;       // [m][Z1] partner offset relative to the active site
+    const int8_t* pdisp;       // [m][Z1][4] partner cell displacement and basis
+    const double* Dtab;        // [K][K][S][K]: V_s[q][t] - V_s[p][t]
+    uint8_t* ws;               // workspace base (padded copies)
+    const double* beta;        // beta[js * beta_stride + r]
+    int64_t* stats;            // [R][3]
+    smcx_tie* ties;
+    int32_t* tie_count;
+    const uint32_t* sweep_counter;  // when set, first sweep index is read here
+    uint64_t seed;
+    uint32_t first_sweep;
+    int32_t n_sweeps;
+    int32_t beta_stride;
+    int32_t tie_cap;
+    int32_t R, K, S, Z1, sumZ;
+    int32_t T[3];              // tile shape (link cells)
+    int32_t LP, WY, WZ;        // LDS window: row pitch, rows per plane, planes
+    int32_t lds_d, lds_offp, lds_offb, lds_pd, lds_mult, lds_win;  // dynamic-LDS byte offsets
+    int32_t g;                 // mini-step (stream / plain launches)
+    int32_t tau_begin, tau_end; // persistent launches: mini-step range of every sweep
+    int32_t only_rep;          // plain launches: the replica, else -1
+    int32_t xcd_per;           // stream launches: logical tiles per XCD chunk
+};
+
+// Dynamic LDS layout helpers (byte offsets, 16-aligned).
+struct LdsLayout {
+    int d_off, offp_off, offb_off, pd_off, mult_off, win_off, total;
+};
+
+inline LdsLayout lds_layout(int lattice, int K, int S, int Z1, int sumZ, int win_bytes)
+{
+    auto al = [](int v) { return (v + 15) & ~15; };
+    const int m = lattice == SMCX_BCC ? 2 : 4;
+    LdsLayout L{};
+    int o = 0;
+    L.d_off = o;    o = al(o + 8 * K * K * S * K);
+    L.offp_off = o; o = al(o + 2 * m * Z1 * sumZ);
+    L.offb_off = o; o = al(o + 4 * m * Z1);
+    L.pd_off = o;   o = al(o + 4 * m * Z1);
+    L.mult_off = o; o = al(o + kMaxShells * kMaxZ1);
+    L.win_off = o;  o = al(o + win_bytes);
+    L.total = o;
+    return L;
+}
+
+}  // namespace smcx

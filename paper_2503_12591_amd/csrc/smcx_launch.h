@@ -1,0 +1,23 @@
+// Host-side launchers of the libsmcx kernels (defined in smcx_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "smcx_internal.h"
+
+namespace smcx {
+
+hipError_t launch_sweep(int lattice, int K, bool persistent, dim3 grid, size_t lds, hipStream_t st,
+                        const SweepArgs& a);
+hipError_t set_sweep_lds_limit(int lattice, int K, size_t lds);
+hipError_t launch_pack(int lattice, bool unpack, uint8_t* occ, uint8_t* ws, const RepDev* reps, int r,
+                       int64_t ncell, hipStream_t st);
+hipError_t launch_validate(const uint8_t* occ, int64_t n, int K, int32_t* bad, hipStream_t st);
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+hipError_t launch_advance_counter(uint32_t* counter, uint32_t n, hipStream_t st);
+hipError_t launch_pair_counts(int lattice, int K, int S, const uint8_t* occ, int64_t N, const int32_t* L,
+                              int B, int64_t* counts, hipStream_t st);
+
+}  // namespace smcx

@@ -1,0 +1,366 @@
+"""ctypes binding of libsmcx (C ABI in include/smcx.h).
+
+Argument marshalling only: torch supplies device memory and the stream, every
+step of the Monte Carlo path runs in the library's HIP kernels.  The module
+fails loudly when the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmcx.so")
+
+BCC, FCC = 0, 1
+MODE_AUTO, MODE_STREAM, MODE_PERSISTENT, MODE_PLAIN = 0, 1, 2, 3
+MODES = {"auto": MODE_AUTO, "stream": MODE_STREAM, "persistent": MODE_PERSISTENT, "plain": MODE_PLAIN}
+TIE_DTYPE = np.dtype([("replica", "<i4"), ("sweep", "<u4"), ("site", "<i8"), ("decision", "<i4"),
+                      ("pad", "<i4")])
+
+EXPORTS = [
+    "smcx_version", "smcx_last_error", "smcx_min_cell_edge", "smcx_workspace_size",
+    "smcx_lattice_init", "smcx_lattice_destroy", "smcx_get_schedule", "smcx_set_epi", "smcx_sweep",
+    "smcx_sweep_partial",
+    "smcx_pair_counts", "smcx_energy", "smcx_sro", "smcx_energy_backward", "smcx_ladder_capture",
+    "smcx_graph_launch", "smcx_graph_destroy", "smcx_timing_enable", "smcx_timing_read",
+]
+
+
+class SmcxError(RuntimeError):
+    pass
+
+
+class Desc(C.Structure):
+    _fields_ = [("lattice", C.c_int32), ("n_species", C.c_int32), ("n_shells", C.c_int32),
+                ("n_replicas", C.c_int32), ("dims", C.c_void_p), ("ell", C.c_void_p),
+                ("ncell", C.c_void_p), ("cells", C.c_void_p), ("tile", C.c_int32 * 3),
+                ("flags", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsmcx.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SmcxError(f"{LIB_PATH} is not built; run `python -m paper_2503_12591_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    p, i32, u32, u64, sz = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c_size_t
+    L.smcx_version.argtypes = []
+    L.smcx_last_error.argtypes = []
+    L.smcx_last_error.restype = C.c_char_p
+    L.smcx_min_cell_edge.argtypes = [i32, i32]
+    L.smcx_workspace_size.argtypes = [C.POINTER(Desc), C.POINTER(sz)]
+    L.smcx_lattice_init.argtypes = [C.POINTER(p), C.POINTER(Desc), p, p, sz, p]
+    L.smcx_lattice_destroy.argtypes = [p]
+    L.smcx_get_schedule.argtypes = [p, i32, p, p, p]
+    L.smcx_set_epi.argtypes = [p, p, p]
+    L.smcx_sweep.argtypes = [p, i32, u64, u32, p, p, p, i32, p, i32, p]
+    L.smcx_sweep_partial.argtypes = [p, u32, i32, i32, u64, p, p, p, i32, p, i32, p]
+    L.smcx_pair_counts.argtypes = [p, p, p]
+    L.smcx_energy.argtypes = [p, p, p, p]
+    L.smcx_sro.argtypes = [p, p, p, p]
+    L.smcx_energy_backward.argtypes = [i32, p, i32, i32, p, i32, p, p]
+    L.smcx_ladder_capture.argtypes = [p, i32, u64, p, p, p, p, i32, p, p, C.POINTER(p)]
+    L.smcx_graph_launch.argtypes = [p, p]
+    L.smcx_graph_destroy.argtypes = [p]
+    L.smcx_timing_enable.argtypes = [p, i32]
+    L.smcx_timing_read.argtypes = [p, p, p]
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = lib().smcx_last_error().decode(errors="replace")
+        raise SmcxError(f"libsmcx error {rc}: {msg}")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise SmcxError("no GPU visible: libsmcx runs on gfx950 devices only")
+    return torch
+
+
+def _stream(torch):
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(np.asarray(a, dtype=dtype))
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def min_cell_edge(lattice: int, n_shells: int) -> int:
+    v = lib().smcx_min_cell_edge(lattice, n_shells)
+    if v < 0:
+        _check(v)
+    return v
+
+
+class Lattice:
+    """R replicas of one lattice kind and energy model, resident on the GPU.
+
+    occ: host uint8 array of all replicas back to back (or a torch uint8 CUDA
+    tensor, used in place).
+    """
+
+    def __init__(self, lattice: int, dims, K: int, S: int, occ, ell=None, cells=None,
+                 tile=(0, 0, 0)):
+        torch = _torch()
+        self.torch = torch
+        dims = np.asarray(dims, dtype=np.int32).reshape(-1, 3)
+        self.R = dims.shape[0]
+        self.lattice, self.K, self.S = lattice, K, S
+        self.dims = dims
+        self.m = 2 if lattice == BCC else 4
+        self.N = (self.m * dims.prod(axis=1)).astype(np.int64)
+        if isinstance(occ, torch.Tensor):
+            assert occ.dtype == torch.uint8 and occ.is_cuda and occ.is_contiguous()
+            self.occ = occ
+        else:
+            self.occ = torch.from_numpy(np.ascontiguousarray(occ, dtype=np.uint8)).cuda()
+        if self.occ.numel() != int(self.N.sum()):
+            raise SmcxError("occupancy size does not match dims")
+        self._keep = []
+        self._dims_arr, dptr = _host(dims, np.int32)
+        d = Desc()
+        d.lattice, d.n_species, d.n_shells, d.n_replicas = lattice, K, S, self.R
+        d.dims = dptr
+        if ell is not None:
+            arr, ptr = _host(np.broadcast_to(np.asarray(ell, np.int32), (self.R,)), np.int32)
+            self._keep.append(arr)
+            d.ell = ptr
+        if cells is not None:
+            # cells: per replica a list of three arrays of edges
+            nc = np.array([[len(c[a]) for a in range(3)] for c in cells], np.int32)
+            flat = np.concatenate([np.asarray(c[a], np.int32) for c in cells for a in range(3)])
+            a1, p1 = _host(nc, np.int32)
+            a2, p2 = _host(flat, np.int32)
+            self._keep += [a1, a2]
+            d.ncell, d.cells = p1, p2
+        for a in range(3):
+            d.tile[a] = int(tile[a])
+        self._desc = d
+        nbytes = C.c_size_t(0)
+        _check(lib().smcx_workspace_size(C.byref(d), C.byref(nbytes)))
+        self.ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device="cuda")
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        h = C.c_void_p()
+        _check(lib().smcx_lattice_init(C.byref(h), C.byref(d), _ptr(self.occ), C.c_void_p(self._ws_ptr),
+                                       nbytes.value, _stream(torch)))
+        self.h = h
+        self.ws_bytes = int(nbytes.value)
+        self.counts = torch.zeros(self.R * S * K * K, dtype=torch.int64, device="cuda")
+        self.V = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().smcx_lattice_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- configuration ----------------------------------------------------
+    def schedule(self, r: int = 0):
+        """(cells as three arrays of edges, n_ministeps) used by replica r."""
+        nc = np.zeros(3, np.int32)
+        cells = np.zeros(int(self.dims[r].sum()), np.int32)
+        nA = np.zeros(1, np.int32)
+        _check(lib().smcx_get_schedule(self.h, r, nc.ctypes.data_as(C.c_void_p),
+                                       cells.ctypes.data_as(C.c_void_p), nA.ctypes.data_as(C.c_void_p)))
+        out, pos = [], 0
+        for a in range(3):
+            out.append(cells[pos:pos + nc[a]].copy())
+            pos += nc[a]
+        return out, int(nA[0])
+
+    def set_epi(self, V):
+        V = np.ascontiguousarray(np.asarray(V, dtype=np.float64).reshape(self.S, self.K, self.K))
+        _check(lib().smcx_set_epi(self.h, V.ctypes.data_as(C.c_void_p), _stream(self.torch)))
+        self.V = V.copy()
+
+    # -- Monte Carlo ------------------------------------------------------
+    def sweep(self, n_sweeps: int, seed: int, betas, first_sweep: int = 0, mode="auto",
+              tie_cap: int = 4096, stats=None, ties=None, tie_count=None):
+        """Run n_sweeps sweeps.  betas: [n_sweeps][R] (or [n_sweeps] for R = 1,
+        or a CUDA float64 tensor of that shape).  Returns (stats, ties,
+        tie_count) device tensors unless given."""
+        torch = self.torch
+        if isinstance(betas, torch.Tensor):
+            b = betas.to(device="cuda", dtype=torch.float64).contiguous()
+        else:
+            b = torch.from_numpy(np.array(
+                np.broadcast_to(np.asarray(betas, np.float64).reshape(n_sweeps, -1),
+                                (n_sweeps, self.R)))).cuda()
+        if stats is None:
+            stats = torch.zeros(self.R * 3, dtype=torch.int64, device="cuda")
+        if ties is None:
+            ties = torch.zeros(max(tie_cap, 1) * TIE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        if tie_count is None:
+            tie_count = torch.zeros(1, dtype=torch.int32, device="cuda")
+        mode = MODES[mode] if isinstance(mode, str) else int(mode)
+        _check(lib().smcx_sweep(self.h, n_sweeps, C.c_uint64(seed), C.c_uint32(first_sweep), _ptr(b),
+                                _ptr(stats), _ptr(ties), tie_cap, _ptr(tie_count), mode,
+                                _stream(torch)))
+        self._last_beta = b  # keep alive until the stream has consumed it
+        return stats, ties, tie_count
+
+    def sweep_partial(self, sweep: int, tau_begin: int, tau_end: int, seed: int, betas, mode="auto",
+                      tie_cap: int = 4096, stats=None, ties=None, tie_count=None):
+        """Mini-steps [tau_begin, tau_end) of global sweep `sweep`; betas: [R]."""
+        torch = self.torch
+        b = torch.from_numpy(np.array(
+            np.broadcast_to(np.asarray(betas, np.float64).reshape(-1), (self.R,)))).cuda()
+        if stats is None:
+            stats = torch.zeros(self.R * 3, dtype=torch.int64, device="cuda")
+        if ties is None:
+            ties = torch.zeros(max(tie_cap, 1) * TIE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        if tie_count is None:
+            tie_count = torch.zeros(1, dtype=torch.int32, device="cuda")
+        mode = MODES[mode] if isinstance(mode, str) else int(mode)
+        _check(lib().smcx_sweep_partial(self.h, C.c_uint32(sweep), tau_begin, tau_end, C.c_uint64(seed),
+                                        _ptr(b), _ptr(stats), _ptr(ties), tie_cap, _ptr(tie_count), mode,
+                                        _stream(torch)))
+        self._last_beta = b
+        return stats, ties, tie_count
+
+    @staticmethod
+    def ties_to_numpy(ties, tie_count):
+        n = int(tie_count.item())
+        raw = ties.cpu().numpy().view(TIE_DTYPE)
+        return raw[:min(n, len(raw))].copy(), n
+
+    # -- observables ------------------------------------------------------
+    def pair_counts(self):
+        _check(lib().smcx_pair_counts(self.h, _ptr(self.counts), _stream(self.torch)))
+        return self.counts.view(self.R, self.S, self.K, self.K)
+
+    def energy(self) -> np.ndarray:
+        E = np.zeros(self.R, np.float64)
+        _check(lib().smcx_energy(self.h, _ptr(self.counts), E.ctypes.data_as(C.c_void_p),
+                                 _stream(self.torch)))
+        return E
+
+    def sro(self) -> np.ndarray:
+        a = np.zeros((self.R, self.S, self.K, self.K), np.float64)
+        _check(lib().smcx_sro(self.h, _ptr(self.counts), a.ctypes.data_as(C.c_void_p),
+                              _stream(self.torch)))
+        return a
+
+    def occupancy(self) -> np.ndarray:
+        return self.occ.cpu().numpy()
+
+    # -- timing -----------------------------------------------------------
+    def timing(self, enable: bool):
+        _check(lib().smcx_timing_enable(self.h, 1 if enable else 0))
+
+    def timing_read(self):
+        ms = np.zeros(1, np.float64)
+        n = np.zeros(1, np.int64)
+        _check(lib().smcx_timing_read(self.h, ms.ctypes.data_as(C.c_void_p), n.ctypes.data_as(C.c_void_p)))
+        return float(ms[0]), int(n[0])
+
+
+class LadderGraph:
+    """A captured persistent ladder launch (fixed beta per replica)."""
+
+    def __init__(self, lat: Lattice, n_sweeps: int, seed: int, betas, first_sweep: int = 0,
+                 tie_cap: int = 4096):
+        torch = lat.torch
+        self.lat = lat
+        self.beta = torch.from_numpy(np.ascontiguousarray(np.asarray(betas, np.float64))).cuda()
+        self.counter = torch.tensor([first_sweep], dtype=torch.int32, device="cuda")
+        self.stats = torch.zeros(lat.R * 3, dtype=torch.int64, device="cuda")
+        self.ties = torch.zeros(max(tie_cap, 1) * TIE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        self.tie_count = torch.zeros(1, dtype=torch.int32, device="cuda")
+        g = C.c_void_p()
+        # the legacy default stream cannot be captured: capture on a side stream
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            _check(lib().smcx_ladder_capture(lat.h, n_sweeps, C.c_uint64(seed), _ptr(self.beta),
+                                             _ptr(self.counter), _ptr(self.stats), _ptr(self.ties),
+                                             tie_cap, _ptr(self.tie_count), _stream(torch),
+                                             C.byref(g)))
+        torch.cuda.current_stream().wait_stream(side)
+        self.g = g
+        self.n_sweeps = n_sweeps
+
+    def launch(self):
+        _check(lib().smcx_graph_launch(self.g, _stream(self.lat.torch)))
+
+    def close(self):
+        if getattr(self, "g", None):
+            lib().smcx_graph_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def energy_backward_counts(lattice: int, dims, K: int, S: int, occ_batch):
+    """Pair counts C[B][S][K][K] (int64 CUDA tensor) of a batch of
+    configurations (uint8 CUDA tensor [B][N]); dE_b/dV = C_b / 2."""
+    torch = _torch()
+    assert occ_batch.dtype == torch.uint8 and occ_batch.is_cuda
+    occ_batch = occ_batch.contiguous()
+    B = occ_batch.shape[0]
+    counts = torch.empty((B, S, K, K), dtype=torch.int64, device="cuda")
+    d, dp = _host(np.asarray(dims, np.int32).reshape(3), np.int32)
+    _check(lib().smcx_energy_backward(lattice, dp, K, S, _ptr(occ_batch), B, _ptr(counts),
+                                      _stream(torch)))
+    return counts
+
+
+def _make_energy_fn():
+    import torch
+
+    class EnergyFn(torch.autograd.Function):
+        """E_b = 1/2 <C_b, V> for a batch of configurations; dE_b/dV = C_b / 2.
+
+        The counts come from the HIP pair-count kernel; the forward product and
+        the backward scaling are the only torch arithmetic."""
+
+        @staticmethod
+        def forward(ctx, V, occ_batch, lattice, dims):
+            S, K, _ = V.shape
+            counts = energy_backward_counts(lattice, dims, K, S, occ_batch).to(V.dtype)
+            ctx.save_for_backward(counts)
+            return 0.5 * (counts * V.unsqueeze(0)).sum(dim=(1, 2, 3))
+
+        @staticmethod
+        def backward(ctx, g):
+            (counts,) = ctx.saved_tensors
+            return 0.5 * (g.view(-1, 1, 1, 1) * counts).sum(dim=0), None, None, None
+
+    return EnergyFn
+
+
+_energy_fn = None
+
+
+def EnergyFn():
+    global _energy_fn
+    if _energy_fn is None:
+        _energy_fn = _make_energy_fn()
+    return _energy_fn

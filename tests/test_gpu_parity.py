@@ -1,0 +1,237 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI (GPU).
+
+Bar: pair counts, trajectories (occupancy after the run and after every
+sweep), attempted / accepted counts and near-tie counts identical; energies
+and Warren-Cowley SRO within 1e-12 relative (in practice identical, since
+they are formed from identical integer counts in the same order).
+"""
+import numpy as np
+import pytest
+
+from gpu_cases import NTHREADS, gpu_vs_oracle, rand_occ, say, sym_V
+from oracle import oracle as O
+from paper_2503_12591_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+BCC, FCC = 0, 1
+
+
+@pytest.fixture(scope="module")
+def smcx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2503_12591_amd import smcx as S
+    S.lib()
+    return S
+
+
+@pytest.mark.parametrize("lattice,dims,K,S", [
+    (BCC, (8, 8, 8), 4, 2), (BCC, (5, 6, 7), 4, 4), (FCC, (6, 5, 7), 5, 4), (BCC, (2, 2, 2), 2, 4),
+    (FCC, (2, 3, 2), 3, 4), (BCC, (9, 4, 3), 8, 3), (FCC, (4, 4, 4), 8, 1), (BCC, (33, 17, 9), 2, 4),
+])
+def test_pair_counts_energy_sro(smcx, lattice, dims, K, S):
+    N = int(np.prod(dims)) * (2 if lattice == BCC else 4)
+    occ = rand_occ(N, K, 7, equi=True)
+    V = sym_V(S, K, 0.05, 3)
+    say(f"pair_counts lattice={lattice} dims={dims} K={K} S={S}")
+    lat = smcx.Lattice(lattice, dims, K, S, occ)
+    lat.set_epi(V)
+    C = lat.pair_counts().cpu().numpy()[0]
+    ref = O.pair_counts(lattice, dims, K, S, occ)
+    assert np.array_equal(C, ref)
+    E = lat.energy()[0]
+    Eref = O.energy(ref, V)
+    assert abs(E - Eref) <= 1e-12 * max(1.0, abs(Eref))
+    Z, _ = O.shells(lattice, S)
+    if (np.bincount(occ, minlength=K) > 0).all():
+        a = lat.sro()[0]
+        aref = O.sro(ref, Z)
+        assert np.allclose(a, aref, rtol=1e-12, atol=1e-12)
+    lat.close()
+
+
+def test_pair_counts_multi_replica(smcx):
+    dims = np.array([[5, 5, 5], [8, 6, 7], [4, 4, 9]], np.int32)
+    K, S = 4, 4
+    occs = [rand_occ(int(2 * np.prod(d)), K, 11 + r) for r, d in enumerate(dims)]
+    say("pair_counts multi-replica")
+    lat = smcx.Lattice(BCC, dims, K, S, np.concatenate(occs))
+    lat.set_epi(sym_V(S, K, 0.05, 1))
+    C = lat.pair_counts().cpu().numpy()
+    for r in range(3):
+        assert np.array_equal(C[r], O.pair_counts(BCC, dims[r], K, S, occs[r]))
+    lat.close()
+
+
+def test_energy_backward_batch_and_autograd(smcx):
+    import torch
+    dims, K, S, B = (5, 4, 6), 4, 4, 7
+    N = 2 * 5 * 4 * 6
+    occs = np.stack([rand_occ(N, K, 100 + b) for b in range(B)])
+    say("energy_backward batch")
+    t = torch.from_numpy(occs).cuda()
+    C = smcx.energy_backward_counts(BCC, dims, K, S, t).cpu().numpy()
+    for b in range(B):
+        assert np.array_equal(C[b], O.pair_counts(BCC, dims, K, S, occs[b]))
+    V = torch.tensor(sym_V(S, K, 0.05, 2), dtype=torch.float64, device="cuda", requires_grad=True)
+    E = smcx.EnergyFn().apply(V, t, BCC, dims)
+    g = torch.arange(1, B + 1, dtype=torch.float64, device="cuda")
+    (E * g).sum().backward()
+    expect = 0.5 * (np.arange(1, B + 1)[:, None, None, None] * C).sum(axis=0)
+    assert np.allclose(V.grad.cpu().numpy(), expect, rtol=0, atol=1e-9)
+    Eref = [O.energy(C[b], V.detach().cpu().numpy()) for b in range(B)]
+    assert np.allclose(E.detach().cpu().numpy(), Eref, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("mode", ["persistent", "stream", "plain"])
+def test_small_bcc_case_every_sweep(smcx, mode):
+    """BCC 8^3, 4 species, 2 shells, 1000 K: identical after every sweep."""
+    w = I.c1_small_bcc()
+    n = 100 if mode == "persistent" else 12
+    gpu_vs_oracle(w.lattice, w.dims, w.K, w.S, w.occ(), w.V, w.betas[:n], seed=w.mc_seed,
+                  mode=mode, check_every_sweep=True)
+
+
+def test_small_bcc_case_full_run(smcx):
+    w = I.c1_small_bcc()
+    gpu_vs_oracle(w.lattice, w.dims, w.K, w.S, w.occ(), w.V, w.betas, seed=w.mc_seed,
+                  mode="persistent")
+
+
+@pytest.mark.parametrize("lattice,dims,K,S,ell,tile,mode", [
+    (FCC, (6, 5, 7), 5, 4, 3, (0, 0, 0), "persistent"),
+    (FCC, (6, 5, 7), 5, 4, 3, (2, 2, 2), "stream"),
+    (FCC, (9, 8, 7), 4, 2, 4, (3, 1, 2), "stream"),
+    (BCC, (11, 9, 13), 4, 4, 3, (4, 2, 3), "stream"),       # uneven cells 3/4 and 4/5
+    (BCC, (17, 10, 9), 4, 4, 4, (16, 4, 4), "stream"),
+    (BCC, (19, 7, 6), 3, 3, 5, (1, 1, 1), "persistent"),
+    (BCC, (10, 10, 10), 8, 4, 3, (8, 4, 2), "stream"),       # 64-bit counters
+    (FCC, (5, 5, 6), 7, 3, 3, (0, 0, 0), "persistent"),
+    (BCC, (2, 2, 2), 2, 4, 4, (0, 0, 0), "persistent"),      # partner images in shell 4
+    (BCC, (2, 3, 2), 3, 4, 4, (0, 0, 0), "stream"),
+    (FCC, (2, 2, 3), 3, 4, 4, (0, 0, 0), "persistent"),
+    (BCC, (3, 3, 3), 4, 4, 3, (1, 1, 1), "persistent"),
+])
+def test_trajectories_varied_geometry(smcx, lattice, dims, K, S, ell, tile, mode):
+    N = int(np.prod(dims)) * (2 if lattice == BCC else 4)
+    occ = rand_occ(N, K, sum(dims), equi=False)
+    V = sym_V(S, K, 0.04, K + S)
+    betas = I.beta_of_T(np.linspace(2500, 600, 6))
+    gpu_vs_oracle(lattice, dims, K, S, occ, V, betas, seed=12345, mode=mode, ell=ell, tile=tile,
+                  first_sweep=3)
+
+
+def test_explicit_partition(smcx):
+    dims = (12, 10, 9)
+    cells = [np.array([3, 5, 4]), np.array([4, 3, 3]), np.array([9])]
+    occ = rand_occ(2 * 12 * 10 * 9, 4, 5)
+    V = sym_V(4, 4, 0.04, 9)
+    gpu_vs_oracle(BCC, dims, 4, 4, occ, V, I.beta_of_T([900.0] * 4), seed=77, mode="stream",
+                  cells=cells, tile=(2, 2, 1))
+
+
+def test_seed_sweep_and_replica_keys_change_the_stream(smcx):
+    """Different seeds / first sweep give different trajectories (the key and
+    counter are really used), each still matching the oracle."""
+    w = I.c1_small_bcc()
+    a = gpu_vs_oracle(w.lattice, w.dims, w.K, w.S, w.occ(), w.V, w.betas[:3], seed=1)
+    b = gpu_vs_oracle(w.lattice, w.dims, w.K, w.S, w.occ(), w.V, w.betas[:3], seed=2)
+    c = gpu_vs_oracle(w.lattice, w.dims, w.K, w.S, w.occ(), w.V, w.betas[:3], seed=1, first_sweep=9)
+    assert not np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+def test_partial_sweeps_compose(smcx):
+    w = I.c1_small_bcc()
+    from paper_2503_12591_amd import smcx as S
+    say("partial sweeps")
+    occ0 = w.occ()
+    full = S.Lattice(w.lattice, w.dims, w.K, w.S, occ0)
+    full.set_epi(w.V)
+    full.sweep(1, 0, w.betas[:1], first_sweep=4, mode="stream")
+    parts = S.Lattice(w.lattice, w.dims, w.K, w.S, occ0)
+    parts.set_epi(w.V)
+    _, nA = parts.schedule(0)
+    for lo, hi in [(0, 37), (37, 38), (38, nA)]:
+        parts.sweep_partial(4, lo, hi, 0, w.betas[:1], mode="persistent")
+    assert np.array_equal(full.occupancy(), parts.occupancy())
+    full.close()
+    parts.close()
+
+
+def ladder_inputs(R, lo, hi, seed=3):
+    g = np.random.default_rng(seed)
+    edges = g.integers(lo, hi + 1, size=R)
+    dims = np.stack([edges, np.roll(edges, 1), np.roll(edges, 2)], axis=1).astype(np.int32)
+    K, S = 4, 4
+    occs = [rand_occ(int(2 * np.prod(d)), K, 1000 + r) for r, d in enumerate(dims)]
+    V = sym_V(S, K, 0.02, 4)
+    betas = I.beta_of_T(300.0 * 10.0 ** (np.arange(R) / max(R - 1, 1)))
+    return dims, K, S, occs, V, betas
+
+
+@pytest.mark.parametrize("mode", ["persistent", "stream", "plain"])
+def test_ladder_replicas_match_oracle(smcx, mode):
+    dims, K, S, occs, V, betas = ladder_inputs(6, 4, 11)
+    n = 3
+    say(f"ladder R=6 mode={mode}")
+    lat = smcx.Lattice(BCC, dims, K, S, np.concatenate(occs))
+    lat.set_epi(V)
+    bt = np.tile(betas, (n, 1))
+    stats, ties, tc = lat.sweep(n, 99, bt, first_sweep=0, mode=mode)
+    gpu = lat.occupancy()
+    tnp, _ = lat.ties_to_numpy(ties, tc)
+    s = stats.cpu().numpy().reshape(-1, 3)
+    off = 0
+    for r in range(len(dims)):
+        cells, _ = lat.schedule(r)
+        ref = occs[r].copy()
+        res = O.run(BCC, dims[r], K, S, cells, ref, V, 99, bt[:, r], replica=r,
+                    replay=tnp[tnp["replica"] == r])
+        N = len(ref)
+        assert np.array_equal(gpu[off:off + N], ref), f"replica {r}"
+        assert s[r, 0] == res.stats[0] and s[r, 1] == res.stats[1]
+        off += N
+    lat.close()
+
+
+def test_ladder_graph_replays_continue_the_chain(smcx):
+    import torch
+    dims, K, S, occs, V, betas = ladder_inputs(5, 5, 9, seed=8)
+    say("ladder graph")
+    lat = smcx.Lattice(BCC, dims, K, S, np.concatenate(occs))
+    lat.set_epi(V)
+    g = smcx.LadderGraph(lat, 2, 31, betas, first_sweep=0)
+    for rep in range(3):
+        g.launch()
+        torch.cuda.synchronize()
+        _ = lat.pair_counts().cpu()  # eager work between replays
+    assert int(g.counter.item()) == 6
+    gpu = lat.occupancy()
+    off = 0
+    for r in range(len(dims)):
+        cells, _ = lat.schedule(r)
+        ref = occs[r].copy()
+        O.run(BCC, dims[r], K, S, cells, ref, V, 31, [betas[r]] * 6, replica=r)
+        assert np.array_equal(gpu[off:off + len(ref)], ref), f"replica {r}"
+        off += len(ref)
+    g.close()
+    lat.close()
+
+
+def test_invalid_occupancy_rejected(smcx):
+    occ = np.zeros(2 * 4 * 4 * 4, np.uint8)
+    occ[17] = 4
+    with pytest.raises(smcx.SmcxError):
+        smcx.Lattice(BCC, (4, 4, 4), 4, 2, occ)
+
+
+def test_asymmetric_epi_rejected(smcx):
+    occ = rand_occ(128, 4, 0)
+    lat = smcx.Lattice(BCC, (4, 4, 4), 4, 2, occ)
+    V = sym_V(2, 4, 0.05, 0)
+    V[1, 0, 2] += 1e-9
+    with pytest.raises(smcx.SmcxError):
+        lat.set_epi(V)
+    with pytest.raises(smcx.SmcxError):
+        lat.sweep(1, 0, [1.0])  # EPI not set
+    lat.close()
