@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark: attempted swaps/s of link-cell parallel swap Metropolis on one
+MI355X, with the HBM roofline of the mini-step kernel and the CPU oracle timed
+beside it.
+
+Workload (default): BCC 800^3 conventional cells (1.024e9 sites, uint8), 4
+species equiatomic, EPI on 4 shells (V ~ N(0, 0.02 eV), seed 5), 1200 K,
+link-cell edge 4 (128 mini-steps per sweep).  One step = 10 sweeps followed by
+one short-range-order reduction (pair counts -> Warren-Cowley SRO); 5 steps =
+the 50-sweep run with SRO every 10 sweeps.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sweeps-per-step", type=int, default=10)
+    ap.add_argument("--edge", type=int, default=800, help="conventional cells per axis")
+    ap.add_argument("--ell", type=int, default=4, help="link-cell edge")
+    ap.add_argument("--tile", type=str, default="0,0,0")
+    ap.add_argument("--mode", default="stream", choices=["stream", "persistent", "plain", "auto"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="approximate CPU time budget of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration) and exit")
+    return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n, "launches": 3}))
+
+
+def cpu_baseline(lattice, dims, K, S, cells, occ_host, V, seed, beta, budget_s):
+    """The oracle on a bounded sample of the same workload: the first mini-steps
+    of sweep 0 on the same lattice, all host threads (at most 16)."""
+    from oracle import oracle as O
+    nthreads = max(1, min(16, O.max_threads()))
+    occ = occ_host.copy()
+    t0 = time.perf_counter()
+    r = O.run_ministeps(lattice, dims, K, S, cells, occ, V, seed, beta, 0, 0, 1, nthreads=nthreads)
+    t1 = time.perf_counter() - t0
+    trials = int(r.stats[0])
+    n_more = max(0, int(budget_s / max(t1, 1e-3)) - 1)
+    nA = int(np.prod([max(c) for c in cells])) * (2 if lattice == 0 else 4)
+    n_more = min(n_more, nA - 1)
+    if n_more > 0:
+        t0 = time.perf_counter()
+        r2 = O.run_ministeps(lattice, dims, K, S, cells, occ, V, seed, beta, 0, 1, 1 + n_more,
+                             nthreads=nthreads)
+        t1 += time.perf_counter() - t0
+        trials += int(r2.stats[0])
+    return {"value": trials / t1, "unit": "attempted swaps/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"mini-steps 0..{n_more} of sweep 0 on the same {dims[0]}x{dims[1]}x{dims[2]} "
+                      f"lattice ({trials} trials, {t1:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus N > 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.copy_probe:
+        copy_probe()
+        return
+    from paper_2503_12591_amd import inputs as I
+    from paper_2503_12591_amd import smcx
+
+    lattice, K, S = I.BCC, 4, 4
+    dims = (args.edge,) * 3
+    N = I.n_sites(lattice, dims)
+    V = I.epi(K, S, 0.02, seed=5)
+    T = 1200.0
+    beta = float(I.beta_of_T(T))
+    seed = 0
+    tile = tuple(int(x) for x in args.tile.split(","))
+    print(f"[bench] generating {N} sites", file=sys.stderr, flush=True)
+    occ = I.occupancy_device(I.equiatomic(K, N), seed=0)
+    occ_host = occ.cpu().numpy() if not args.no_cpu_baseline else None
+    lat = smcx.Lattice(lattice, dims, K, S, occ, ell=args.ell, tile=tile)
+    lat.set_epi(V)
+    cells, nA = lat.schedule(0)
+    nC = int(np.prod([len(c) for c in cells]))
+    spst = args.sweeps_per_step
+    betas = torch.full((spst, 1), beta, dtype=torch.float64, device="cuda")
+    stats = torch.zeros(3, dtype=torch.int64, device="cuda")
+    ties = torch.zeros(4096 * 24, dtype=torch.uint8, device="cuda")
+    tie_count = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    sweep_no = 0
+
+    def step():
+        nonlocal sweep_no
+        lat.sweep(spst, seed, betas, first_sweep=sweep_no, mode=args.mode, stats=stats, ties=ties,
+                  tie_count=tie_count)
+        sweep_no += spst
+        return lat.sro()
+
+    print(f"[bench] warmup {args.warmup} step(s)", file=sys.stderr, flush=True)
+    lat.sro()  # SRO of the initial configuration (sweep 0)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st0 = stats.cpu().numpy().copy()
+    print(f"[bench] timing {args.steps} step(s)", file=sys.stderr, flush=True)
+    lat.timing(True)
+    lat.timing_read()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    kern_ms, launches = lat.timing_read()
+    lat.timing(False)
+    st1 = stats.cpu().numpy()
+    attempted = int(st1[0] - st0[0])
+    assert attempted == args.steps * spst * N, (attempted, args.steps * spst * N)
+    secs = ms / 1e3
+    value = attempted / secs
+    avg_launch_s = kern_ms / 1e3 / max(launches, 1)
+    # algorithmic bytes of one mini-step launch: every occupancy byte is read
+    # once (the LIZ+ regions of the active sites cover the lattice) and each
+    # trial writes at most 2 bytes
+    bytes_per_launch = N + 2 * nC
+    achieved = bytes_per_launch / avg_launch_s / 1e9 if args.mode == "stream" else None
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_ministep_bcc{args.edge}_ell{args.ell}.json")
+    if os.path.exists(tfile):
+        with open(tfile) as f:
+            tr = json.load(f)
+        if tr.get("kernel_build") == kernel_fingerprint():
+            traffic = tr["bytes_per_launch"]
+    out = {
+        "metric": "attempted swaps/sec and HBM GB/s fraction; batched ladder vs plain sweep",
+        "value": value,
+        "unit": "attempted swaps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"bcc{args.edge}_k4_s4_T1200_sro10", "lattice": "BCC",
+                   "dims": list(dims), "sites": N, "species": K, "shells": S, "T_K": T,
+                   "sweeps_per_step": spst, "link_cell": args.ell, "n_ministeps": nA,
+                   "n_cells": nC, "mode": args.mode, "tile": list(tile),
+                   "accepted_frac": float(st1[1] - st0[1]) / attempted,
+                   "near_ties": int(tie_count.item())},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": "k_ministep",
+                     "avg_launch_us": avg_launch_s * 1e6, "launches": launches,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(lattice, dims, K, S, cells, occ_host, V, seed, beta,
+                                           args.cpu_seconds)
+    lat.close()
+    print(json.dumps(out), flush=True)
+
+
+def kernel_fingerprint() -> str:
+    """Hash of the kernel sources; counter data is only valid for the build it
+    was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("smcx_kernels.hip", "smcx_internal.h"):
+        with open(os.path.join(ROOT, "paper_2503_12591_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

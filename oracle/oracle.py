@@ -62,6 +62,8 @@ def lib():
         L.or_single_trial.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, u64, u32, u32, i64, dbl]
         L.or_run.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, p, p, u64, u32, u32, i32, p, p,
                              i32, p, p, i32, p, p, i64, i32]
+        L.or_run_ministeps.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, p, p, u64, u32, u32,
+                                       i32, i32, dbl, p, i32, p, p, i32, p, i32]
         L.or_max_threads.argtypes = []
         _lib = L
     return _lib
@@ -198,6 +200,30 @@ def run(lattice, dims, K, S, cells, occ: np.ndarray, V, seed: int, betas, first_
         raise ValueError("or_run failed (bad arguments)")
     nt = int(n_ties[0])
     return RunResult(stats, ties[:min(nt, tie_cap)].copy(), nt, tr if trace else None)
+
+
+def run_ministeps(lattice, dims, K, S, cells, occ: np.ndarray, V, seed: int, beta: float,
+                  sweep: int, tau_begin: int, tau_end: int, replica: int = 0, replay=None,
+                  tie_cap: int = 1024, nthreads: int = 1) -> RunResult:
+    """Mini-steps [tau_begin, tau_end) of one sweep, in place on ``occ``."""
+    assert occ.dtype == np.uint8 and occ.flags.c_contiguous
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    ncell = np.array([len(c) for c in cells], np.int32)
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(c, np.int32) for c in cells]))
+    if replay is None:
+        replay = np.zeros(0, TIE_DTYPE)
+    replay = np.ascontiguousarray(replay, dtype=TIE_DTYPE)
+    stats = np.zeros(3, np.int64)
+    ties = np.zeros(max(tie_cap, 1), TIE_DTYPE)
+    n_ties = np.zeros(1, np.int32)
+    rc = lib().or_run_ministeps(lattice, _ptr(_dims(dims)), K, S, _ptr(ncell), _ptr(flat),
+                                _ptr(occ), _ptr(V), seed, replica, sweep, tau_begin, tau_end, beta,
+                                _ptr(replay), len(replay), _ptr(stats), _ptr(ties), tie_cap,
+                                _ptr(n_ties), nthreads)
+    if rc != 0:
+        raise ValueError("or_run_ministeps failed (bad arguments)")
+    nt = int(n_ties[0])
+    return RunResult(stats, ties[:min(nt, tie_cap)].copy(), nt, None)
 
 
 def max_threads() -> int:

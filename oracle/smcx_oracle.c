@@ -532,15 +532,16 @@ int or_single_trial(int lattice, const int32_t L[3], int K, int S, uint8_t *occ,
  * nthreads > 1 runs the cells of one mini-step on that many OpenMP threads;
  * trials within a mini-step are independent, so the result is identical.
  */
-int or_run(int lattice, const int32_t L[3], int K, int S, const int32_t ncell[3],
-           const int32_t *cells, uint8_t *occ, const double *V, uint64_t seed, uint32_t replica,
-           uint32_t first_sweep, int32_t n_sweeps, const double *beta, const or_tie *replay,
-           int32_t n_replay, int64_t *stats, or_tie *ties, int32_t tie_cap, int32_t *n_ties,
-           or_trace *trace, int64_t trace_cap, int32_t nthreads)
+static int run_range(int lattice, const int32_t L[3], int K, int S, const int32_t ncell[3],
+                     const int32_t *cells, uint8_t *occ, const double *V, uint64_t seed,
+                     uint32_t replica, uint32_t first_sweep, int32_t n_sweeps, int32_t tau_begin,
+                     int32_t tau_end, const double *beta, const or_tie *replay, int32_t n_replay,
+                     int64_t *stats, or_tie *ties, int32_t tie_cap, int32_t *n_ties, or_trace *trace,
+                     int64_t trace_cap, int32_t nthreads)
 {
     or_sys sy;
     if (sys_init(&sy, lattice, L, K, S) != OR_OK) return OR_EARG;
-    if (n_sweeps < 0 || nthreads < 1) return OR_EARG;
+    if (n_sweeps < 0 || nthreads < 1 || tau_begin < 0 || tau_end < tau_begin) return OR_EARG;
     if (trace && nthreads != 1) return OR_EARG;
     for (int64_t i = 0; i < sy.N; ++i)
         if (occ[i] >= K) return OR_EARG;
@@ -585,7 +586,8 @@ int or_run(int lattice, const int32_t L[3], int K, int S, const int32_t ncell[3]
     for (int32_t js = 0; js < n_sweeps; ++js) {
         uint32_t t = first_sweep + (uint32_t)js;
         double bt = beta[js];
-        for (int tau = 0; tau < nA; ++tau) {
+        int tau_hi = tau_end < nA ? tau_end : nA;
+        for (int tau = tau_begin; tau < tau_hi; ++tau) {
             int b = tau % m;
             int rest = tau / m;
             int o[3];
@@ -657,6 +659,31 @@ int or_run(int lattice, const int32_t L[3], int K, int S, const int32_t ncell[3]
     stats[2] += tie;
     if (n_ties) *n_ties = nt;
     return OR_OK;
+}
+
+int or_run(int lattice, const int32_t L[3], int K, int S, const int32_t ncell[3],
+           const int32_t *cells, uint8_t *occ, const double *V, uint64_t seed, uint32_t replica,
+           uint32_t first_sweep, int32_t n_sweeps, const double *beta, const or_tie *replay,
+           int32_t n_replay, int64_t *stats, or_tie *ties, int32_t tie_cap, int32_t *n_ties,
+           or_trace *trace, int64_t trace_cap, int32_t nthreads)
+{
+    return run_range(lattice, L, K, S, ncell, cells, occ, V, seed, replica, first_sweep, n_sweeps, 0,
+                     0x7fffffff, beta, replay, n_replay, stats, ties, tie_cap, n_ties, trace,
+                     trace_cap, nthreads);
+}
+
+/* Mini-steps [tau_begin, tau_end) of the single sweep `sweep` (same
+ * arguments otherwise; beta is the sweep's inverse temperature).  Running
+ * consecutive ranges reproduces the full sweep. */
+int or_run_ministeps(int lattice, const int32_t L[3], int K, int S, const int32_t ncell[3],
+                     const int32_t *cells, uint8_t *occ, const double *V, uint64_t seed,
+                     uint32_t replica, uint32_t sweep, int32_t tau_begin, int32_t tau_end, double beta,
+                     const or_tie *replay, int32_t n_replay, int64_t *stats, or_tie *ties,
+                     int32_t tie_cap, int32_t *n_ties, int32_t nthreads)
+{
+    return run_range(lattice, L, K, S, ncell, cells, occ, V, seed, replica, sweep, 1, tau_begin,
+                     tau_end, &beta, replay, n_replay, stats, ties, tie_cap, n_ties, NULL, 0,
+                     nthreads);
 }
 
 /* Number of OpenMP threads available to the timing variant (1 without

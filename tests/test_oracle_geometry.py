@@ -166,3 +166,25 @@ def test_link_cell_rule_is_tight(oracle, lattice, S):
     dims = (3 * ell, 2 * ell, 2 * ell)
     cells = [np.full(3, ell, np.int32), np.full(2, ell, np.int32), np.full(2, ell, np.int32)]
     assert _conflicts(lattice, dims, S, cells) > 0
+
+
+@pytest.mark.parametrize("lattice,dims,ell", [(BCC, (8, 9, 8), 4), (FCC, (7, 6, 6), 3)])
+def test_ministep_ranges_compose_to_a_sweep(oracle, lattice, dims, ell):
+    K, S = 4, 4
+    N = int(np.prod(dims)) * (2 if lattice == BCC else 4)
+    occ0 = np.random.default_rng(2).integers(0, K, N).astype(np.uint8)
+    V = np.random.default_rng(3).normal(0, 0.05, (S, K, K))
+    V = V + V.transpose(0, 2, 1)
+    cells = oracle.default_cells(dims, ell)
+    nA = int(np.prod([max(c) for c in cells])) * (2 if lattice == BCC else 4)
+    full = occ0.copy()
+    r_full = oracle.run(lattice, dims, K, S, cells, full, V, seed=4, betas=[6.0], first_sweep=2)
+    part = occ0.copy()
+    att = acc = 0
+    for lo, hi in [(0, 5), (5, 6), (6, nA)]:
+        r = oracle.run_ministeps(lattice, dims, K, S, cells, part, V, seed=4, beta=6.0, sweep=2,
+                                 tau_begin=lo, tau_end=hi, nthreads=1 + lo % 3)
+        att += r.stats[0]
+        acc += r.stats[1]
+    assert np.array_equal(full, part)
+    assert att == r_full.stats[0] and acc == r_full.stats[1]
