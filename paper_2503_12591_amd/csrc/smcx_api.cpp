@@ -65,6 +65,7 @@ struct Replica {
 struct Plan {
     int lattice, K, S, R, m, Z1, sumZ;
     int T[3];
+    int block;  // threads per workgroup: the tile's link cells rounded up to whole waves
     std::vector<Replica> reps;
     int LP, WY, WZ;
     LdsLayout lds;
@@ -94,7 +95,7 @@ int make_plan(const smcx_desc* d, Plan& P)
     P.sumZ = sum_Z(G, P.S);
     const int emin = min_edge(P.lattice, P.S);
     if (d->tile[0] == 0 && d->tile[1] == 0 && d->tile[2] == 0) {
-        P.T[0] = 16; P.T[1] = 4; P.T[2] = 4;
+        P.T[0] = 16; P.T[1] = 4; P.T[2] = 2;
     } else {
         for (int a = 0; a < 3; ++a) {
             if (d->tile[a] < 1) return fail(SMCX_E_INVALID_ARG, "tile edges must be >= 1");
@@ -102,6 +103,7 @@ int make_plan(const smcx_desc* d, Plan& P)
         }
         if ((int64_t)P.T[0] * P.T[1] * P.T[2] > kBlock) return fail(SMCX_E_INVALID_ARG, "tile holds more than 256 link cells");
     }
+    P.block = (P.T[0] * P.T[1] * P.T[2] + 63) / 64 * 64;
     P.reps.resize(P.R);
     int64_t occ_off = 0;
     size_t cells_pos = 0;
@@ -205,7 +207,7 @@ int make_plan(const smcx_desc* d, Plan& P)
     P.LP = maxbytes;
     P.WY = maxn[1];
     P.WZ = maxn[2];
-    if (P.LP > 16 * kBlock) return fail(SMCX_E_UNSUPPORTED, "tile window rows longer than 4096 bytes; use a smaller tile");
+    if (P.LP > 4096) return fail(SMCX_E_UNSUPPORTED, "tile window rows longer than 4096 bytes; use a smaller tile");
     const int64_t win = (int64_t)P.LP * P.WY * P.WZ;
     if (win > 160 * 1024) return fail(SMCX_E_UNSUPPORTED, "tile window does not fit in LDS; use a smaller tile");
     P.lds = lds_layout(P.lattice, P.K, P.S, P.Z1, P.sumZ, (int)win);
@@ -259,6 +261,7 @@ struct smcx_lattice {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
     std::vector<hipEvent_t> pool;
     int64_t timed_launches = 0;
+    int stream_wgs = 8;  // stream-mode grid: 8 XCD chunks x workgroups per XCD
 };
 
 namespace {
@@ -288,8 +291,8 @@ SweepArgs base_args(smcx_lattice* h)
     a.lds_offp = P.lds.offp_off;
     a.lds_offb = P.lds.offb_off;
     a.lds_pd = P.lds.pd_off;
-    a.lds_mult = P.lds.mult_off;
     a.lds_win = P.lds.win_off;
+    a.win_bytes = P.lds.win_bytes;
     a.only_rep = -1;
     a.sweep_counter = nullptr;
     return a;
@@ -316,7 +319,7 @@ int timed_launch(smcx_lattice* h, bool persistent, dim3 grid, hipStream_t st, co
         if (!e0 || !e1) return fail(SMCX_E_HIP, "hipEventCreate failed");
         SMCX_HIP(hipEventRecord(e0, st));
     }
-    SMCX_HIP(launch_sweep(h->P.lattice, h->P.K, persistent, grid, h->P.lds.total, st, a));
+    SMCX_HIP(launch_sweep(h->P.lattice, h->P.K, persistent, grid, h->P.block, h->P.lds.total, st, a));
     if (h->timing) {
         SMCX_HIP(hipEventRecord(e1, st));
         h->pending.emplace_back(e0, e1);
@@ -330,7 +333,7 @@ int pack_all(smcx_lattice* h, bool unpack, hipStream_t st)
     const Plan& P = h->P;
     for (int r = 0; r < P.R; ++r) {
         const int64_t ncell = P.reps[r].N / P.m;
-        SMCX_HIP(launch_pack(P.lattice, unpack, h->occ, h->ws, (const RepDev*)(h->ws + P.off_reps), r, ncell, st));
+        SMCX_HIP(launch_pack(P.lattice, P.K, unpack, h->occ, h->ws, (const RepDev*)(h->ws + P.off_reps), r, ncell, st));
     }
     return SMCX_OK;
 }
@@ -413,8 +416,12 @@ int smcx_lattice_init(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_de
         D.occ_off = R.occ_off;
         D.N = R.N;
         D.ntiles = R.ntiles;
+        D.alias = 0;
         for (int s = 0; s < kMaxShells; ++s)
-            for (int k = 0; k < kMaxZ1; ++k) D.mult[s][k] = (uint8_t)R.mult[s][k];
+            for (int k = 0; k < kMaxZ1; ++k) {
+                D.mult[s][k] = (uint8_t)R.mult[s][k];
+                if (k < P.Z1 && R.mult[s][k] != (s == 0 ? 1 : 0)) D.alias = 1;
+            }
         tile_off[r + 1] = tile_off[r] + R.ntiles;
     }
     const Geometry& G = kGeom[P.lattice];
@@ -451,6 +458,12 @@ int smcx_lattice_init(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_de
         return fail(SMCX_E_INVALID_ARG, "occupancy holds a species >= n_species");
     }
     SMCX_HIP(set_sweep_lds_limit(P.lattice, P.K, P.lds.total));
+    // stream grid: every CU filled to the occupancy the LDS footprint allows
+    int dev = 0, cus = 256, per_cu = 1;
+    SMCX_HIP(hipGetDevice(&dev));
+    SMCX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    SMCX_HIP(ministep_occupancy(P.lattice, P.K, P.block, P.lds.total, &per_cu));
+    h->stream_wgs = 8 * std::max(1, (cus / 8) * std::max(1, per_cu));
     *out = h;
     g_err.clear();
     return SMCX_OK;
@@ -548,8 +561,7 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
         a.beta_stride = P.R;
         if (int rc = timed_launch(h, true, dim3(P.R), st, a)) return rc;
     } else if (mode == SMCX_MODE_STREAM) {
-        a.xcd_per = (int32_t)((P.total_tiles + 7) / 8);
-        const dim3 grid((unsigned)(8 * (int64_t)a.xcd_per));
+        const dim3 grid((unsigned)std::min<int64_t>(h->stream_wgs, 8 * ((P.total_tiles + 7) / 8)));
         for (int js = 0; js < n_sweeps; ++js) {
             a.first_sweep = first_sweep + (uint32_t)js;
             a.beta = beta_dev + (int64_t)js * P.R;
@@ -564,8 +576,7 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
             a.beta = beta_dev + (int64_t)js * P.R;
             for (int r = 0; r < P.R; ++r) {
                 a.only_rep = r;
-                a.xcd_per = (int32_t)((P.reps[r].ntiles + 7) / 8);
-                const dim3 grid((unsigned)(8 * (int64_t)a.xcd_per));
+                const dim3 grid((unsigned)std::min<int64_t>(h->stream_wgs, 8 * ((P.reps[r].ntiles + 7) / 8)));
                 for (int g = tau_begin; g < std::min(tau_end, P.reps[r].nA); ++g) {
                     a.g = g;
                     if (int rc = timed_launch(h, false, grid, st, a)) return rc;
@@ -739,7 +750,7 @@ int smcx_ladder_capture(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, const 
     a.tau_end = P.max_nA;
     int rc = pack_all(h, false, st);
     hipError_t e = hipSuccess;
-    if (rc == SMCX_OK) e = launch_sweep(P.lattice, P.K, true, dim3(P.R), P.lds.total, st, a);
+    if (rc == SMCX_OK) e = launch_sweep(P.lattice, P.K, true, dim3(P.R), P.block, P.lds.total, st, a);
     if (rc == SMCX_OK && e == hipSuccess) e = launch_advance_counter(sweep_counter_dev, (uint32_t)n_sweeps, st);
     if (rc == SMCX_OK && e == hipSuccess) rc = pack_all(h, true, st);
     hipGraph_t graph = nullptr;

@@ -140,7 +140,7 @@ struct RepDev {
     int32_t cs_off;      // cell-origin table offset (x: nc0+1 entries, then y, then z)
     int32_t prow;        // padded row pitch (bytes, multiple of 16)
     int32_t prows;       // rows per padded plane (L1 + 2H)
-    int32_t pad0;
+    int32_t alias;       // some partner has images in another shell (an edge of 2)
     int64_t pad_off;     // byte offset of the padded copy in the workspace
     int64_t occ_off;     // first site of this replica in the occupancy array
     int64_t N;           // sites
@@ -171,16 +171,16 @@ struct SweepArgs {
     int32_t R, K, S, Z1, sumZ;
     int32_t T[3];              // tile shape (link cells)
     int32_t LP, WY, WZ;        // LDS window: row pitch, rows per plane, planes
-    int32_t lds_d, lds_offp, lds_offb, lds_pd, lds_mult, lds_win;  // dynamic-LDS byte offsets
+    int32_t lds_d, lds_offp, lds_offb, lds_pd, lds_win;  // dynamic-LDS byte offsets
+    int32_t win_bytes;         // one window buffer (two are used, back to back)
     int32_t g;                 // mini-step (stream / plain launches)
     int32_t tau_begin, tau_end; // persistent launches: mini-step range of every sweep
     int32_t only_rep;          // plain launches: the replica, else -1
-    int32_t xcd_per;           // stream launches: logical tiles per XCD chunk
 };
 
 // Dynamic LDS layout helpers (byte offsets, 16-aligned).
 struct LdsLayout {
-    int d_off, offp_off, offb_off, pd_off, mult_off, win_off, total;
+    int d_off, offp_off, offb_off, pd_off, win_off, win_bytes, total;
 };
 
 inline LdsLayout lds_layout(int lattice, int K, int S, int Z1, int sumZ, int win_bytes)
@@ -193,8 +193,9 @@ inline LdsLayout lds_layout(int lattice, int K, int S, int Z1, int sumZ, int win
     L.offp_off = o; o = al(o + 2 * m * Z1 * sumZ);
     L.offb_off = o; o = al(o + 4 * m * Z1);
     L.pd_off = o;   o = al(o + 4 * m * Z1);
-    L.mult_off = o; o = al(o + kMaxShells * kMaxZ1);
-    L.win_off = o;  o = al(o + win_bytes);
+    L.win_off = o;
+    L.win_bytes = al(win_bytes);
+    o = al(o + 2 * L.win_bytes);  // two window buffers
     L.total = o;
     return L;
 }

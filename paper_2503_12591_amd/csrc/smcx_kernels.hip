@@ -53,12 +53,31 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     o0 = c0; o1 = c1; o2 = c2; o3 = c3;
 }
 
-template <int NW> struct CounterT;
-template <> struct CounterT<1> { using T = uint32_t; static constexpr uint32_t bias = 0x80808080u; };
-template <> struct CounterT<2> {
-    using T = uint64_t;
-    static constexpr uint64_t bias = 0x8080808080808080ull;
+// Packed per-shell neighbour counters: F bits per species, one field per
+// species, biased by `half` when two counters are subtracted so that every
+// field of (n_a + bias - n_b) stays in [half - 24, half + 24] (a shell has at
+// most 24 sites) and no borrow crosses fields.  Encoding 1: K <= 4, 8-bit
+// fields in 32 bits; 3: K = 5, 6-bit fields in 32 bits; 2: K <= 8, 8-bit
+// fields in 64 bits.  The padded copy and the LDS window hold F * species.
+template <int E> struct Enc;
+template <> struct Enc<1> {
+    using T = uint32_t;
+    static constexpr int F = 8, KP = 4, half = 128;
+    static constexpr uint32_t bias = 0x80808080u, mask = 0xFF;
 };
+template <> struct Enc<3> {
+    using T = uint32_t;
+    static constexpr int F = 6, KP = 5, half = 32;
+    static constexpr uint32_t bias = 32u | 32u << 6 | 32u << 12 | 32u << 18 | 32u << 24, mask = 0x3F;
+};
+template <> struct Enc<2> {
+    using T = uint64_t;
+    static constexpr int F = 8, KP = 8, half = 128;
+    static constexpr uint64_t bias = 0x8080808080808080ull, mask = 0xFF;
+};
+
+// species from its stored form F * species (F = 8 or 6, species < 8)
+__device__ __forceinline__ int species_of(int v, int F) { return F == 8 ? v >> 3 : (v * 43) >> 8; }
 
 // Write one species value to a site and to every periodic image of it that
 // lies inside the padded copy.
@@ -83,6 +102,17 @@ __device__ __forceinline__ void store_site(uint8_t* pad, const RepDev& rep, int 
         }
 }
 
+// acc + (1 << sh) in one instruction (v_lshl_add): the packed counter gains
+// one in the 8-bit field of the neighbour's species (sh = 8 * species).
+__device__ __forceinline__ uint32_t shl1_add(uint32_t sh, uint32_t acc)
+{
+    uint32_t r;
+    asm("v_lshl_add_u32 %0, 1, %1, %2" : "=v"(r) : "v"(sh), "v"(acc));
+    return r;
+}
+
+__device__ __forceinline__ uint64_t shl1_add(uint32_t sh, uint64_t acc) { return acc + ((uint64_t)1 << sh); }
+
 // Packed neighbour counters of a basis-B site at LDS byte `base`: A[s] gets
 // 1 << (8 * species) per neighbour of shell s.  Offsets are compile-time
 // displacements times the launch-uniform window pitches.
@@ -99,7 +129,7 @@ __device__ __forceinline__ void count_uniform(const uint8_t* win, int base, int 
             for (int n = 0; n < G.Z[s]; ++n) {
                 const Nb nb = nb_of(G, B, G.v[s][n][0], G.v[s][n][1], G.v[s][n][2]);
                 const int off = nb.dz * PL + nb.dy * LP + G.m * nb.dx + (nb.bt - B);
-                acc += (CT)1 << win[base + off];
+                acc = shl1_add(win[base + off], acc);
             }
         }
         A[s] = acc;
@@ -119,7 +149,7 @@ __device__ __forceinline__ void count_table(const uint8_t* win, int base, const 
         CT acc = 0;
         if (s < S) {
 #pragma unroll
-            for (int n = 0; n < G.Z[s]; ++n) acc += (CT)1 << win[base + offs[j + n]];
+            for (int n = 0; n < G.Z[s]; ++n) acc = shl1_add(win[base + offs[j + n]], acc);
         }
         j += G.Z[s];
         A[s] = acc;
@@ -131,8 +161,6 @@ struct Lds {
     const int16_t* offP;
     const int32_t* offB;
     const int8_t* pd;
-    const uint8_t* mult;
-    uint8_t* win;
 };
 
 __device__ __forceinline__ Lds lds_ptrs(const SweepArgs& A, uint8_t* smem)
@@ -142,14 +170,12 @@ __device__ __forceinline__ Lds lds_ptrs(const SweepArgs& A, uint8_t* smem)
     l.offP = (const int16_t*)(smem + A.lds_offp);
     l.offB = (const int32_t*)(smem + A.lds_offb);
     l.pd = (const int8_t*)(smem + A.lds_pd);
-    l.mult = smem + A.lds_mult;
-    l.win = smem + A.lds_win;
     return l;
 }
 
-// Copy the launch tables and the replica's partner-image counts into LDS.
+// Copy the launch tables into LDS (a barrier follows before first use).
 template <int LAT>
-__device__ void load_tables(const SweepArgs& A, const RepDev& rep, uint8_t* smem)
+__device__ void load_tables(const SweepArgs& A, uint8_t* smem)
 {
     constexpr int m = kGeom[LAT].m;
     double* D = (double*)(smem + A.lds_d);
@@ -164,28 +190,98 @@ __device__ void load_tables(const SweepArgs& A, const RepDev& rep, uint8_t* smem
     int8_t* pd = (int8_t*)(smem + A.lds_pd);
     for (int i = threadIdx.x; i < m * A.Z1; i += blockDim.x) Bo[i] = A.offB[i];
     for (int i = threadIdx.x; i < 4 * m * A.Z1; i += blockDim.x) pd[i] = A.pdisp[i];
-    uint8_t* mu = smem + A.lds_mult;
-    for (int i = threadIdx.x; i < kMaxShells * kMaxZ1; i += blockDim.x)
-        mu[i] = rep.mult[i / kMaxZ1][i % kMaxZ1];
 }
 
 struct TileGeom {
-    int w0[3];  // window origin (replica conventional cells, >= -H)
-    int n[3];   // window extent
-    int gx0;    // first staged byte of each padded row
+    int w0[3];   // window origin (replica conventional cells, >= -H)
+    int n[3];    // window extent
+    int gx0;     // first staged byte of each padded row
+    int c0[3];   // first link cell of the tile
+    int c1[3];   // one past the last link cell
+    int n16;     // staged 16-byte chunks per row
 };
 
-// One lane's trial.  Returns flags: bit0 active, bit1 accepted, bit2 near-tie.
+// Window of one tile for mini-step offsets o: identical in every thread.
+// Returns false when no cell of the tile has these offsets.
+template <int LAT>
+__device__ __forceinline__ bool tile_geometry(const SweepArgs& A, const RepDev& rep, int64_t tile,
+                                              const int (&o)[3], TileGeom& tg)
+{
+    constexpr int m = kGeom[LAT].m;
+    const int tx = (int)(tile % rep.ntile[0]);
+    const int64_t trest = tile / rep.ntile[0];
+    const int ty = (int)(trest % rep.ntile[1]);
+    const int tz = (int)(trest / rep.ntile[1]);
+    tg.c0[0] = tx * A.T[0];
+    tg.c0[1] = ty * A.T[1];
+    tg.c0[2] = tz * A.T[2];
+    const int32_t* org = A.origins + rep.cs_off;
+    bool any = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        tg.c1[a] = min(tg.c0[a] + A.T[a], rep.nc[a]);
+        tg.w0[a] = org[tg.c0[a]] + o[a] - kHalo;
+        const int w1 = min(org[tg.c1[a] - 1] + o[a] + kHalo + 1, rep.L[a] + kHalo);
+        tg.n[a] = w1 - tg.w0[a];
+        any &= tg.n[a] > 0;
+        org += rep.nc[a] + 1;
+    }
+    tg.gx0 = (m * (tg.w0[0] + kHalo)) & ~15;
+    const int gx1 = (m * (tg.w0[0] + tg.n[0] + kHalo) + 15) & ~15;
+    tg.n16 = (gx1 - tg.gx0) >> 4;
+    return any;
+}
+
+// Issue the window loads of a tile straight into LDS (global_load_lds_dwordx4:
+// lane i of a wave writes the 16 bytes at M0 + 16 i).  Window slot j (16
+// bytes at buf + 16 j) is row R = j / LPc, chunk j % LPc; row R holds window
+// plane R / WY, row R % WY.  The loads complete asynchronously; the caller
+// waits on vmcnt and a barrier before reading the buffer.
+__device__ __forceinline__ void stage_async(const SweepArgs& A, const RepDev& rep, const TileGeom& tg,
+                                            const uint8_t* pad, uint8_t* buf)
+{
+    const int LPc = A.LP >> 4;
+    const int nslots = A.WZ * A.WY * LPc;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int step = blockDim.x;
+    int j = wave * 64 + lane;
+    int R = j / LPc, col = j - R * LPc;
+    int wz = R / A.WY, wy = R - wz * A.WY;
+    const int dR = step / LPc, dcol = step - dR * LPc;
+    const uint8_t* base = pad + ((int64_t)(tg.w0[2] + kHalo) * rep.prows + (tg.w0[1] + kHalo)) * rep.prow + tg.gx0;
+    const int64_t plane = (int64_t)rep.prows * rep.prow;
+    for (int jb = wave * 64; jb < nslots; jb += step) {
+        if (jb + lane < nslots && col < tg.n16 && wy < tg.n[1] && wz < tg.n[2]) {
+            const uint8_t* src = base + wz * plane + (int64_t)wy * rep.prow + 16 * col;
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                             (__attribute__((address_space(3))) void*)(buf + 16 * jb), 16, 0, 0);
+        }
+        col += dcol;
+        wy += dR;
+        if (col >= LPc) {
+            col -= LPc;
+            ++wy;
+        }
+        while (wy >= A.WY) {
+            wy -= A.WY;
+            ++wz;
+        }
+    }
+}
+
+// One lane's trial on the staged window `win`.  Returns flags: bit0 active,
+// bit1 accepted, bit2 near-tie.
 template <int LAT, int NW, int B>
 __device__ __forceinline__ int lane_trial(const SweepArgs& A, const RepDev& rep, uint8_t* pad,
-                                          const Lds& T, const TileGeom& tg, int r, uint32_t t,
-                                          double beta, int ax, int ay, int az)
+                                          const Lds& T, const uint8_t* win, const TileGeom& tg, int r,
+                                          uint32_t t, double beta, int ax, int ay, int az)
 {
-    using CT = typename CounterT<NW>::T;
+    using EN = Enc<NW>;
+    using CT = typename EN::T;
     constexpr Geometry G = kGeom[LAT];
     constexpr int m = G.m;
     const int LP = A.LP, PL = A.LP * A.WY;
-    const uint8_t* win = T.win;
     const int la = ((az - tg.w0[2]) * A.WY + (ay - tg.w0[1])) * LP + (m * (ax + kHalo) + B - tg.gx0);
     const int64_t ia = B + (int64_t)m * (ax + (int64_t)rep.L[0] * (ay + (int64_t)rep.L[1] * az));
 
@@ -209,19 +305,20 @@ __device__ __forceinline__ int lane_trial(const SweepArgs& A, const RepDev& rep,
     }
 
     // species were checked < K at init; the clamp keeps table reads in bounds regardless
-    const int p = min(p8 >> 3, A.K - 1), q = min(q8 >> 3, A.K - 1);
+    const int p = min(species_of(p8, EN::F), A.K - 1), q = min(species_of(q8, EN::F), A.K - 1);
     const double* Dp = T.D + (size_t)((p * A.K + q) * A.S) * A.K;
-    constexpr int KP = NW == 1 ? 4 : 8;
+    constexpr int KP = EN::KP;
     double dE = 0.0;
 #pragma unroll
     for (int s = 0; s < kMaxShells; ++s) {
         if (s < A.S) {
-            const CT mu = (CT)T.mult[s * kMaxZ1 + k];
-            const CT d = Ca[s] + CounterT<NW>::bias - Cb[s] + (mu << p8) - (mu << q8);
+            // images of the partner inside shell s (1, 0, 0, 0 unless an edge is 2)
+            const CT mu = rep.alias ? (CT)rep.mult[s][k] : (CT)(s == 0 ? 1 : 0);
+            const CT d = Ca[s] + EN::bias - Cb[s] + (mu << p8) - (mu << q8);
 #pragma unroll
             for (int tt = 0; tt < KP; ++tt) {
                 if (tt < A.K) {
-                    const int c = (int)((d >> (8 * tt)) & 0xFF) - 128;
+                    const int c = (int)((d >> (EN::F * tt)) & EN::mask) - EN::half;
                     dE = dE + (double)c * Dp[s * A.K + tt];
                 }
             }
@@ -258,163 +355,191 @@ __device__ __forceinline__ int lane_trial(const SweepArgs& A, const RepDev& rep,
         bx += bx < 0 ? rep.L[0] : (bx >= rep.L[0] ? -rep.L[0] : 0);
         by += by < 0 ? rep.L[1] : (by >= rep.L[1] ? -rep.L[1] : 0);
         bz += bz < 0 ? rep.L[2] : (bz >= rep.L[2] ? -rep.L[2] : 0);
-        store_site(pad, rep, m, ax, ay, az, B, (uint8_t)q);
-        store_site(pad, rep, m, bx, by, bz, bb, (uint8_t)p);
+        // the padded copy holds 8 * species, like the window
+        store_site(pad, rep, m, ax, ay, az, B, (uint8_t)q8);
+        store_site(pad, rep, m, bx, by, bz, bb, (uint8_t)p8);
     }
     return 1 | (acc ? 2 : 0) | (tie ? 4 : 0);
 }
 
 template <int LAT, int NW>
 __device__ __forceinline__ int lane_dispatch(int b, const SweepArgs& A, const RepDev& rep, uint8_t* pad,
-                                             const Lds& T, const TileGeom& tg, int r, uint32_t t,
-                                             double beta, int ax, int ay, int az)
+                                             const Lds& T, const uint8_t* win, const TileGeom& tg, int r,
+                                             uint32_t t, double beta, int ax, int ay, int az)
 {
     if constexpr (LAT == SMCX_BCC) {
-        if (b == 0) return lane_trial<LAT, NW, 0>(A, rep, pad, T, tg, r, t, beta, ax, ay, az);
-        return lane_trial<LAT, NW, 1>(A, rep, pad, T, tg, r, t, beta, ax, ay, az);
+        if (b == 0) return lane_trial<LAT, NW, 0>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
+        return lane_trial<LAT, NW, 1>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
     } else {
         switch (b) {
-        case 0: return lane_trial<LAT, NW, 0>(A, rep, pad, T, tg, r, t, beta, ax, ay, az);
-        case 1: return lane_trial<LAT, NW, 1>(A, rep, pad, T, tg, r, t, beta, ax, ay, az);
-        case 2: return lane_trial<LAT, NW, 2>(A, rep, pad, T, tg, r, t, beta, ax, ay, az);
-        default: return lane_trial<LAT, NW, 3>(A, rep, pad, T, tg, r, t, beta, ax, ay, az);
+        case 0: return lane_trial<LAT, NW, 0>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
+        case 1: return lane_trial<LAT, NW, 1>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
+        case 2: return lane_trial<LAT, NW, 2>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
+        default: return lane_trial<LAT, NW, 3>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
         }
     }
 }
 
-// Process one tile of one mini-step: stage the window into LDS, run the
-// lanes' trials, add the statistics.  Every thread of the block calls it with
-// the same arguments; it starts and ends with a block barrier.
-template <int LAT, int NW>
-__device__ void run_tile(const SweepArgs& A, const RepDev& rep, int r, int64_t tile, int tau,
-                         uint32_t t, double beta, const Lds& T)
+// Per-thread trial statistics, flushed with one wave reduction and three
+// atomics per wave.
+struct Stats {
+    int att = 0, acc = 0, tie = 0;
+};
+
+__device__ __forceinline__ int wave_sum_i(int v)
 {
-    constexpr int m = kGeom[LAT].m;
-    const int b = tau % m;
-    int rest = tau / m;
-    const int o[3] = {rest % rep.M[0], (rest / rep.M[0]) % rep.M[1], rest / (rep.M[0] * rep.M[1])};
-
-    const int tx = (int)(tile % rep.ntile[0]);
-    const int64_t trest = tile / rep.ntile[0];
-    const int ty = (int)(trest % rep.ntile[1]);
-    const int tz = (int)(trest / rep.ntile[1]);
-    const int c0[3] = {tx * A.T[0], ty * A.T[1], tz * A.T[2]};
-    int c1[3];
-    const int32_t* org[3];
-    org[0] = A.origins + rep.cs_off;
-    org[1] = org[0] + rep.nc[0] + 1;
-    org[2] = org[1] + rep.nc[1] + 1;
-    TileGeom tg;
-    bool empty = false;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        c1[a] = min(c0[a] + A.T[a], rep.nc[a]);
-        tg.w0[a] = org[a][c0[a]] + o[a] - kHalo;
-        const int w1 = min(org[a][c1[a] - 1] + o[a] + kHalo + 1, rep.L[a] + kHalo);
-        tg.n[a] = w1 - tg.w0[a];
-        empty |= tg.n[a] <= 0;
-    }
-    if (empty) return;  // uniform across the block
-    tg.gx0 = (m * (tg.w0[0] + kHalo)) & ~15;
-    const int gx1 = (m * (tg.w0[0] + tg.n[0] + kHalo) + 15) & ~15;
-    const int n16 = (gx1 - tg.gx0) >> 4;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
 
-    uint8_t* pad = A.ws + rep.pad_off;
-    __syncthreads();  // the previous tile's lanes are done with the window
-    {
-        // stage: 16-byte loads, species shifted left by 3 (8 * sigma)
-        const int per = blockDim.x / n16;
-        const int col = threadIdx.x % n16;
-        int row = threadIdx.x / n16;
-        const int nrows = tg.n[1] * tg.n[2];
-        if (row < per) {
-            int wy = row % tg.n[1];
-            int wz = row / tg.n[1];
-            for (; row < nrows; row += per) {
-                const uint8_t* src =
-                    pad + ((int64_t)(tg.w0[2] + wz + kHalo) * rep.prows + (tg.w0[1] + wy + kHalo)) * rep.prow +
-                    tg.gx0 + 16 * col;
-                uint4 v = *(const uint4*)src;
-                v.x = (v.x << 3) & 0xF8F8F8F8u;
-                v.y = (v.y << 3) & 0xF8F8F8F8u;
-                v.z = (v.z << 3) & 0xF8F8F8F8u;
-                v.w = (v.w << 3) & 0xF8F8F8F8u;
-                *(uint4*)(T.win + (wz * A.WY + wy) * A.LP + 16 * col) = v;
-                wy += per;
-                while (wy >= tg.n[1]) {
-                    wy -= tg.n[1];
-                    ++wz;
-                }
-            }
-        }
+__device__ __forceinline__ void flush_stats(const SweepArgs& A, int r, Stats& st)
+{
+    const int a = wave_sum_i(st.att), c = wave_sum_i(st.acc), t = wave_sum_i(st.tie);
+    if ((threadIdx.x & 63) == 0 && r >= 0) {
+        unsigned long long* p = (unsigned long long*)(A.stats + 3 * (int64_t)r);
+        if (a) atomicAdd(p + 0, (unsigned long long)a);
+        if (c) atomicAdd(p + 1, (unsigned long long)c);
+        if (t) atomicAdd(p + 2, (unsigned long long)t);
     }
-    __syncthreads();
+    st = Stats();
+}
 
+// Trials of the lanes of one staged tile.
+template <int LAT, int NW>
+__device__ __forceinline__ void tile_trials(const SweepArgs& A, const RepDev& rep, int r, const TileGeom& tg,
+                                            int b, const int (&o)[3], uint32_t t, double beta, const Lds& T,
+                                            const uint8_t* win, Stats& st)
+{
     const int l = threadIdx.x;
     const int lx = l % A.T[0];
     const int ly = (l / A.T[0]) % A.T[1];
     const int lz = l / (A.T[0] * A.T[1]);
-    const int cx = c0[0] + lx, cy = c0[1] + ly, cz = c0[2] + lz;
-    bool active = lz < A.T[2] && cx < c1[0] && cy < c1[1] && cz < c1[2];
-    int ax = 0, ay = 0, az = 0;
-    if (active) {
-        ax = org[0][cx] + o[0];
-        ay = org[1][cy] + o[1];
-        az = org[2][cz] + o[2];
-        active = ax < org[0][cx + 1] && ay < org[1][cy + 1] && az < org[2][cz + 1];
-    }
-    int f = 0;
-    if (active) f = lane_dispatch<LAT, NW>(b, A, rep, pad, T, tg, r, t, beta, ax, ay, az);
+    const int cx = tg.c0[0] + lx, cy = tg.c0[1] + ly, cz = tg.c0[2] + lz;
+    if (!(lz < A.T[2] && cx < tg.c1[0] && cy < tg.c1[1] && cz < tg.c1[2])) return;
+    const int32_t* ox = A.origins + rep.cs_off;
+    const int32_t* oy = ox + rep.nc[0] + 1;
+    const int32_t* oz = oy + rep.nc[1] + 1;
+    const int ax = ox[cx] + o[0], ay = oy[cy] + o[1], az = oz[cz] + o[2];
+    if (!(ax < ox[cx + 1] && ay < oy[cy + 1] && az < oz[cz + 1])) return;
+    uint8_t* pad = A.ws + rep.pad_off;
+    const int f = lane_dispatch<LAT, NW>(b, A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
+    st.att += 1;
+    st.acc += (f >> 1) & 1;
+    st.tie += (f >> 2) & 1;
+}
 
-    const uint64_t att = __ballot(f & 1), accm = __ballot(f & 2), tiem = __ballot(f & 4);
-    if ((threadIdx.x & 63) == 0 && att) {
-        unsigned long long* st = (unsigned long long*)(A.stats + 3 * (int64_t)r);
-        atomicAdd(st + 0, (unsigned long long)__popcll(att));
-        if (accm) atomicAdd(st + 1, (unsigned long long)__popcll(accm));
-        if (tiem) atomicAdd(st + 2, (unsigned long long)__popcll(tiem));
+// Tiles first, first + step, ... (< end) of a logical tile space for mini-step
+// tau of sweep t, window loads double-buffered: the next tile's window streams
+// into LDS while the current tile's trials run.  tile_of(i, r, tile) maps a
+// logical index to (replica, tile of that replica); beta_of(r) gives the
+// replica's inverse temperature.  Every thread calls this with the same
+// arguments; it ends with all of its global writes issued.
+template <int LAT, int NW, typename TileOf, typename BetaOf>
+__device__ void run_tiles(const SweepArgs& A, int64_t first, int64_t end, int64_t step, int tau_fixed,
+                          uint32_t t, const Lds& T, uint8_t* win0, uint8_t* win1, TileOf tile_of, BetaOf beta_of,
+                          Stats& st, int& r_stats)
+{
+    constexpr int m = kGeom[LAT].m;
+    if (first >= end) return;
+    int r, rn;
+    int64_t tile, tilen;
+    tile_of(first, r, tile);
+    int tau = tau_fixed;
+    auto offsets = [&](const RepDev& rep, int (&o)[3], int& b) {
+        b = tau % m;
+        const int rest = tau / m;
+        o[0] = rest % rep.M[0];
+        o[1] = (rest / rep.M[0]) % rep.M[1];
+        o[2] = rest / (rep.M[0] * rep.M[1]);
+    };
+    int o[3], b;
+    TileGeom tg;
+    bool have = false;
+    {
+        const RepDev& rep = A.reps[r];
+        offsets(rep, o, b);
+        have = tau < rep.nA && tile_geometry<LAT>(A, rep, tile, o, tg);
+        if (have) stage_async(A, rep, tg, A.ws + rep.pad_off, win0);
+    }
+    int k = 0;
+    for (int64_t i = first; i < end; i += step, ++k) {
+        const int64_t inext = i + step;
+        int on[3], bn;
+        TileGeom tgn;
+        bool haven = false;
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();  // window of tile i landed; all lanes done with the other buffer
+        uint8_t* cur = (k & 1) ? win1 : win0;
+        uint8_t* nxt = (k & 1) ? win0 : win1;
+        if (inext < end) {
+            tile_of(inext, rn, tilen);
+            const RepDev& repn = A.reps[rn];
+            offsets(repn, on, bn);
+            haven = tau < repn.nA && tile_geometry<LAT>(A, repn, tilen, on, tgn);
+            if (haven) stage_async(A, repn, tgn, A.ws + repn.pad_off, nxt);
+        }
+        if (have) {
+            if (r != r_stats) {
+                flush_stats(A, r_stats, st);
+                r_stats = r;
+            }
+            tile_trials<LAT, NW>(A, A.reps[r], r, tg, b, o, t, beta_of(r), T, cur, st);
+        }
+        r = rn;
+        tile = tilen;
+        tg = tgn;
+        have = haven;
+        o[0] = on[0]; o[1] = on[1]; o[2] = on[2];
+        b = bn;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Stream mode: one launch per mini-step g, one workgroup per tile over all
-// replicas.  Logical tiles are handed out so that consecutive tiles (which
-// share halo rows) run on the same XCD: hardware workgroup i goes to XCD
-// i % 8, so logical tile = (i % 8) * xcd_per + i / 8.
+// Stream mode: one launch per mini-step g.  The logical tiles of all replicas
+// (or of one replica in plain mode) are split into 8 contiguous chunks, one
+// per XCD (hardware workgroup i runs on XCD i % 8); the workgroups of an XCD
+// walk their chunk together with stride W, so neighbouring tiles -- which
+// share halo rows -- are in flight on the same L2 at the same time.
 // ---------------------------------------------------------------------------
 template <int LAT, int NW>
 __global__ __launch_bounds__(kBlock) void k_ministep(SweepArgs A)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    const int64_t i = blockIdx.x;
-    int64_t tile = (i % 8) * (int64_t)A.xcd_per + i / 8;
-    int r;
-    if (A.only_rep >= 0) {
-        r = A.only_rep;
-        if (tile >= A.reps[r].ntiles) return;
-    } else {
-        if (tile >= A.tile_off[A.R]) return;
-        int lo = 0, hi = A.R - 1;  // last r with tile_off[r] <= tile
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (A.tile_off[mid] <= tile) lo = mid; else hi = mid - 1;
-        }
-        r = lo;
-        tile -= A.tile_off[r];
-    }
-    const RepDev& rep = A.reps[r];
-    if (A.g >= rep.nA) return;
-    load_tables<LAT>(A, rep, smem);
+    load_tables<LAT>(A, smem);
     const Lds T = lds_ptrs(A, smem);
-    __syncthreads();
-    const double beta = A.beta[r];  // host passes the sweep's row
-    run_tile<LAT, NW>(A, rep, r, tile, A.g, A.first_sweep, beta, T);
+    const int64_t total = A.only_rep >= 0 ? A.reps[A.only_rep].ntiles : A.tile_off[A.R];
+    const int xcd = blockIdx.x % 8;
+    const int64_t W = gridDim.x / 8;
+    const int64_t chunk = (total + 7) / 8;
+    const int64_t lo = xcd * chunk;
+    const int64_t hi = min(lo + chunk, total);
+    auto tile_of = [&](int64_t i, int& r, int64_t& tile) {
+        if (A.only_rep >= 0) {
+            r = A.only_rep;
+            tile = i;
+            return;
+        }
+        int a = 0, z = A.R - 1;  // last replica with tile_off[r] <= i
+        while (a < z) {
+            const int mid = (a + z + 1) >> 1;
+            if (A.tile_off[mid] <= i) a = mid; else z = mid - 1;
+        }
+        r = a;
+        tile = i - A.tile_off[a];
+    };
+    auto beta_of = [&](int r) { return A.beta[r]; };
+    Stats st;
+    int r_stats = -1;
+    run_tiles<LAT, NW>(A, lo + blockIdx.x / 8, hi, W, A.g, A.first_sweep, T, smem + A.lds_win,
+                       smem + A.lds_win + A.win_bytes, tile_of, beta_of, st, r_stats);
+    flush_stats(A, r_stats, st);
 }
 
 // ---------------------------------------------------------------------------
 // Persistent mode: one workgroup per replica runs every sweep and mini-step;
-// the replica's tiles of one mini-step are processed one after another and
 // block barriers order the mini-steps (all writes of a replica come from its
-// own workgroup).
+// own workgroup, and a barrier makes them visible to its later loads).
 // ---------------------------------------------------------------------------
 template <int LAT, int NW>
 __global__ __launch_bounds__(kBlock) void k_persistent(SweepArgs A)
@@ -422,18 +547,28 @@ __global__ __launch_bounds__(kBlock) void k_persistent(SweepArgs A)
     extern __shared__ __align__(16) uint8_t smem[];
     const int r = blockIdx.x;
     const RepDev& rep = A.reps[r];
-    load_tables<LAT>(A, rep, smem);
+    load_tables<LAT>(A, smem);
     const Lds T = lds_ptrs(A, smem);
-    __syncthreads();
     const uint32_t first = A.sweep_counter ? *A.sweep_counter : A.first_sweep;
+    auto tile_of = [&](int64_t i, int& rr, int64_t& tile) {
+        rr = r;
+        tile = i;
+    };
+    Stats st;
+    int r_stats = r;
+    const int tau_end = min(A.tau_end, rep.nA);
     for (int js = 0; js < A.n_sweeps; ++js) {
         const uint32_t t = first + (uint32_t)js;
         const double beta = A.beta[(int64_t)js * A.beta_stride + r];
-        const int tau_end = min(A.tau_end, rep.nA);
-        for (int tau = A.tau_begin; tau < tau_end; ++tau)
-            for (int64_t tile = 0; tile < rep.ntiles; ++tile)
-                run_tile<LAT, NW>(A, rep, r, tile, tau, t, beta, T);
+        auto beta_of = [&](int) { return beta; };
+        for (int tau = A.tau_begin; tau < tau_end; ++tau) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();  // the previous mini-step's writes are visible to every wave
+            run_tiles<LAT, NW>(A, 0, rep.ntiles, 1, tau, t, T, smem + A.lds_win, smem + A.lds_win + A.win_bytes,
+                               tile_of, beta_of, st, r_stats);
+        }
     }
+    flush_stats(A, r_stats, st);
 }
 
 __global__ void k_advance_counter(uint32_t* counter, uint32_t n)
@@ -443,7 +578,7 @@ __global__ void k_advance_counter(uint32_t* counter, uint32_t n)
 
 // Natural layout -> padded copy (all halo images).
 template <int M>
-__global__ void k_pack(const uint8_t* occ, uint8_t* ws, const RepDev* reps, int r)
+__global__ void k_pack(const uint8_t* occ, uint8_t* ws, const RepDev* reps, int r, int F)
 {
     const RepDev& rep = reps[r];
     uint8_t* pad = ws + rep.pad_off;
@@ -456,13 +591,13 @@ __global__ void k_pack(const uint8_t* occ, uint8_t* ws, const RepDev* reps, int 
         const int y = (int)(cr % rep.L[1]);
         const int z = (int)(cr / rep.L[1]);
 #pragma unroll
-        for (int b = 0; b < M; ++b) store_site(pad, rep, M, x, y, z, b, o[M * c + b]);
+        for (int b = 0; b < M; ++b) store_site(pad, rep, M, x, y, z, b, (uint8_t)(o[M * c + b] * F));
     }
 }
 
 // Padded copy interior -> natural layout.
 template <int M>
-__global__ void k_unpack(uint8_t* occ, const uint8_t* ws, const RepDev* reps, int r)
+__global__ void k_unpack(uint8_t* occ, const uint8_t* ws, const RepDev* reps, int r, int F)
 {
     const RepDev& rep = reps[r];
     const uint8_t* pad = ws + rep.pad_off;
@@ -476,7 +611,7 @@ __global__ void k_unpack(uint8_t* occ, const uint8_t* ws, const RepDev* reps, in
         const int z = (int)(cr / rep.L[1]);
         const uint8_t* row = pad + ((int64_t)(z + kHalo) * rep.prows + (y + kHalo)) * rep.prow + M * (x + kHalo);
 #pragma unroll
-        for (int b = 0; b < M; ++b) o[M * c + b] = row[b];
+        for (int b = 0; b < M; ++b) o[M * c + b] = (uint8_t)species_of(row[b], F);
     }
 }
 
@@ -595,57 +730,85 @@ __global__ __launch_bounds__(kBlock) void k_pair_counts(const uint8_t* occ, int6
 // Host-side launchers
 // ---------------------------------------------------------------------------
 template <int LAT, int NW>
-static hipError_t launch_sweep_t(bool persistent, dim3 grid, size_t lds, hipStream_t st, const SweepArgs& a)
+static hipError_t launch_sweep_t(bool persistent, dim3 grid, int block, size_t lds, hipStream_t st,
+                                 const SweepArgs& a)
 {
     if (persistent) {
-        hipLaunchKernelGGL((k_persistent<LAT, NW>), grid, dim3(kBlock), lds, st, a);
+        hipLaunchKernelGGL((k_persistent<LAT, NW>), grid, dim3(block), lds, st, a);
     } else {
-        hipLaunchKernelGGL((k_ministep<LAT, NW>), grid, dim3(kBlock), lds, st, a);
+        hipLaunchKernelGGL((k_ministep<LAT, NW>), grid, dim3(block), lds, st, a);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int lattice, int K, bool persistent, dim3 grid, size_t lds, hipStream_t st,
+int encoding_of(int K) { return K <= 4 ? 1 : (K == 5 ? 3 : 2); }
+int field_bits_of(int K) { return K == 5 ? 6 : 8; }
+
+hipError_t launch_sweep(int lattice, int K, bool persistent, dim3 grid, int block, size_t lds, hipStream_t st,
                         const SweepArgs& a)
 {
-    const int nw = K <= 4 ? 1 : 2;
-    if (lattice == SMCX_BCC)
-        return nw == 1 ? launch_sweep_t<SMCX_BCC, 1>(persistent, grid, lds, st, a)
-                       : launch_sweep_t<SMCX_BCC, 2>(persistent, grid, lds, st, a);
-    return nw == 1 ? launch_sweep_t<SMCX_FCC, 1>(persistent, grid, lds, st, a)
-                   : launch_sweep_t<SMCX_FCC, 2>(persistent, grid, lds, st, a);
+    const int e = encoding_of(K);
+    if (lattice == SMCX_BCC) {
+        if (e == 1) return launch_sweep_t<SMCX_BCC, 1>(persistent, grid, block, lds, st, a);
+        if (e == 3) return launch_sweep_t<SMCX_BCC, 3>(persistent, grid, block, lds, st, a);
+        return launch_sweep_t<SMCX_BCC, 2>(persistent, grid, block, lds, st, a);
+    }
+    if (e == 1) return launch_sweep_t<SMCX_FCC, 1>(persistent, grid, block, lds, st, a);
+    if (e == 3) return launch_sweep_t<SMCX_FCC, 3>(persistent, grid, block, lds, st, a);
+    return launch_sweep_t<SMCX_FCC, 2>(persistent, grid, block, lds, st, a);
+}
+
+template <int LAT, int E>
+static void sweep_kernels(const void*& f1, const void*& f2)
+{
+    f1 = (const void*)k_ministep<LAT, E>;
+    f2 = (const void*)k_persistent<LAT, E>;
+}
+
+static void sweep_kernels_for(int lattice, int K, const void*& f1, const void*& f2)
+{
+    const int e = encoding_of(K);
+    if (lattice == SMCX_BCC) {
+        if (e == 1) sweep_kernels<SMCX_BCC, 1>(f1, f2);
+        else if (e == 3) sweep_kernels<SMCX_BCC, 3>(f1, f2);
+        else sweep_kernels<SMCX_BCC, 2>(f1, f2);
+    } else {
+        if (e == 1) sweep_kernels<SMCX_FCC, 1>(f1, f2);
+        else if (e == 3) sweep_kernels<SMCX_FCC, 3>(f1, f2);
+        else sweep_kernels<SMCX_FCC, 2>(f1, f2);
+    }
 }
 
 hipError_t set_sweep_lds_limit(int lattice, int K, size_t lds)
 {
-    const int nw = K <= 4 ? 1 : 2;
-    const void* f1;
-    const void* f2;
-    if (lattice == SMCX_BCC) {
-        f1 = nw == 1 ? (const void*)k_ministep<SMCX_BCC, 1> : (const void*)k_ministep<SMCX_BCC, 2>;
-        f2 = nw == 1 ? (const void*)k_persistent<SMCX_BCC, 1> : (const void*)k_persistent<SMCX_BCC, 2>;
-    } else {
-        f1 = nw == 1 ? (const void*)k_ministep<SMCX_FCC, 1> : (const void*)k_ministep<SMCX_FCC, 2>;
-        f2 = nw == 1 ? (const void*)k_persistent<SMCX_FCC, 1> : (const void*)k_persistent<SMCX_FCC, 2>;
-    }
+    const void *f1, *f2;
+    sweep_kernels_for(lattice, K, f1, f2);
     hipError_t e = hipFuncSetAttribute(f1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute(f2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t launch_pack(int lattice, bool unpack, uint8_t* occ, uint8_t* ws, const RepDev* reps, int r,
+hipError_t ministep_occupancy(int lattice, int K, int block, size_t lds, int* blocks_per_cu)
+{
+    const void *f1, *f2;
+    sweep_kernels_for(lattice, K, f1, f2);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f1, block, lds);
+}
+
+hipError_t launch_pack(int lattice, int K, bool unpack, uint8_t* occ, uint8_t* ws, const RepDev* reps, int r,
                        int64_t ncell, hipStream_t st)
 {
     int64_t nb = (ncell + kBlock - 1) / kBlock;
     if (nb > 65536) nb = 65536;
     if (nb < 1) nb = 1;
     const dim3 g((unsigned)nb), b(kBlock);
+    const int F = field_bits_of(K);
     if (lattice == SMCX_BCC) {
-        if (unpack) hipLaunchKernelGGL(k_unpack<2>, g, b, 0, st, occ, ws, reps, r);
-        else hipLaunchKernelGGL(k_pack<2>, g, b, 0, st, occ, ws, reps, r);
+        if (unpack) hipLaunchKernelGGL(k_unpack<2>, g, b, 0, st, occ, ws, reps, r, F);
+        else hipLaunchKernelGGL(k_pack<2>, g, b, 0, st, occ, ws, reps, r, F);
     } else {
-        if (unpack) hipLaunchKernelGGL(k_unpack<4>, g, b, 0, st, occ, ws, reps, r);
-        else hipLaunchKernelGGL(k_pack<4>, g, b, 0, st, occ, ws, reps, r);
+        if (unpack) hipLaunchKernelGGL(k_unpack<4>, g, b, 0, st, occ, ws, reps, r, F);
+        else hipLaunchKernelGGL(k_pack<4>, g, b, 0, st, occ, ws, reps, r, F);
     }
     return hipGetLastError();
 }
