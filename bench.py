@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--ell", type=int, default=4, help="link-cell edge")
     ap.add_argument("--tile", type=str, default="0,0,0")
     ap.add_argument("--mode", default="stream", choices=["stream", "persistent", "plain", "auto"])
+    ap.add_argument("--double-buffer", action="store_true",
+                    help="stream the next tile window in while the current one runs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -104,7 +106,7 @@ def main():
     print(f"[bench] generating {N} sites", file=sys.stderr, flush=True)
     occ = I.occupancy_device(I.equiatomic(K, N), seed=0)
     occ_host = occ.cpu().numpy() if not args.no_cpu_baseline else None
-    lat = smcx.Lattice(lattice, dims, K, S, occ, ell=args.ell, tile=tile)
+    lat = smcx.Lattice(lattice, dims, K, S, occ, ell=args.ell, tile=tile, double_buffer=args.double_buffer)
     lat.set_epi(V)
     cells, nA = lat.schedule(0)
     nC = int(np.prod([len(c) for c in cells]))
@@ -151,10 +153,7 @@ def main():
     secs = ms / 1e3
     value = attempted / secs
     avg_launch_s = kern_ms / 1e3 / max(launches, 1)
-    # algorithmic bytes of one mini-step launch: every occupancy byte is read
-    # once (the LIZ+ regions of the active sites cover the lattice) and each
-    # trial writes at most 2 bytes
-    bytes_per_launch = N + 2 * nC
+    bytes_per_launch = algorithmic_bytes_per_launch(cells, N, 2)
     achieved = bytes_per_launch / avg_launch_s / 1e9 if args.mode == "stream" else None
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_ministep_bcc{args.edge}_ell{args.ell}.json")
@@ -180,6 +179,7 @@ def main():
                    "dims": list(dims), "sites": N, "species": K, "shells": S, "T_K": T,
                    "sweeps_per_step": spst, "link_cell": args.ell, "n_ministeps": nA,
                    "n_cells": nC, "mode": args.mode, "tile": list(tile),
+                   "window_buffers": 2 if args.double_buffer else 1,
                    "accepted_frac": float(st1[1] - st0[1]) / attempted,
                    "near_ties": int(tie_count.item())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -195,6 +195,23 @@ def main():
                                            args.cpu_seconds)
     lat.close()
     print(json.dumps(out), flush=True)
+
+
+def algorithmic_bytes_per_launch(cells, N, m):
+    """Average algorithmic HBM bytes of one mini-step launch.  A mini-step with
+    offsets o reads every occupancy byte of the link cells that have o (the
+    LIZ+ regions of their active sites cover those cells) and writes at most 2
+    bytes per trial; with uniform cells that is N + 2 n_C."""
+    M = [int(max(c)) for c in cells]
+    total = 0.0
+    for oz in range(M[2]):
+        for oy in range(M[1]):
+            for ox in range(M[0]):
+                act = [(np.asarray(cells[a]) > o).sum() for a, o in enumerate((ox, oy, oz))]
+                frac = np.prod([act[a] / len(cells[a]) for a in range(3)])
+                n_act = int(np.prod(act))
+                total += m * (frac * N + 2 * n_act)
+    return total / (m * M[0] * M[1] * M[2])
 
 
 def kernel_fingerprint() -> str:

@@ -106,9 +106,16 @@ typedef struct {
                               axis sums to its dimension and every edge is at
                               least the minimum unless the axis has one cell */
     int32_t tile[3];       /* link cells per workgroup tile along x, y, z
-                              (product <= 256), or {0,0,0} for the default */
-    uint32_t flags;        /* reserved, 0 */
+                              (product <= 256), or {0,0,0} for the default
+                              (16,4,4) on BCC, (16,4,2) on FCC */
+    uint32_t flags;        /* SMCX_FLAG_* bits */
 } smcx_desc;
+
+/* desc.flags: give each workgroup two tile windows, so that the next tile's
+ * window streams into LDS while the current tile's trials run (the default
+ * stages one window at a time, with half the LDS per workgroup and so more
+ * workgroups per CU; both give the same trajectory). */
+#define SMCX_FLAG_DOUBLE_BUFFER 1u
 
 int smcx_version(void);
 

@@ -66,6 +66,8 @@ struct Plan {
     int lattice, K, S, R, m, Z1, sumZ;
     int T[3];
     int block;  // threads per workgroup: the tile's link cells rounded up to whole waves
+    int nbuf;   // window buffers per workgroup
+    int preset; // compile-time window preset of the stream kernel, or -1
     std::vector<Replica> reps;
     int LP, WY, WZ;
     LdsLayout lds;
@@ -84,7 +86,8 @@ int make_plan(const smcx_desc* d, Plan& P)
     if (d->n_replicas < 1) return fail(SMCX_E_INVALID_ARG, "n_replicas must be >= 1");
     if (!d->dims) return fail(SMCX_E_INVALID_ARG, "dims is NULL");
     if ((d->ncell == nullptr) != (d->cells == nullptr)) return fail(SMCX_E_INVALID_ARG, "ncell and cells must both be set or both NULL");
-    if (d->flags != 0) return fail(SMCX_E_INVALID_ARG, "flags must be 0");
+    if (d->flags & ~(uint32_t)SMCX_FLAG_DOUBLE_BUFFER) return fail(SMCX_E_INVALID_ARG, "unknown flags");
+    P.nbuf = (d->flags & SMCX_FLAG_DOUBLE_BUFFER) ? 2 : 1;
     P.lattice = d->lattice;
     P.K = d->n_species;
     P.S = d->n_shells;
@@ -95,7 +98,7 @@ int make_plan(const smcx_desc* d, Plan& P)
     P.sumZ = sum_Z(G, P.S);
     const int emin = min_edge(P.lattice, P.S);
     if (d->tile[0] == 0 && d->tile[1] == 0 && d->tile[2] == 0) {
-        P.T[0] = 16; P.T[1] = 4; P.T[2] = 2;
+        P.T[0] = 16; P.T[1] = 4; P.T[2] = P.lattice == SMCX_BCC ? 4 : 2;
     } else {
         for (int a = 0; a < 3; ++a) {
             if (d->tile[a] < 1) return fail(SMCX_E_INVALID_ARG, "tile edges must be >= 1");
@@ -207,10 +210,28 @@ int make_plan(const smcx_desc* d, Plan& P)
     P.LP = maxbytes;
     P.WY = maxn[1];
     P.WZ = maxn[2];
+    // a compile-time window applies when every replica is cut into uniform
+    // cells of the preset's edge and the tile matches; its (larger or equal)
+    // window dimensions then define the LDS layout and the offset tables
+    P.preset = -1;
+    for (int pi = 0; pi < kNumPresets && P.preset < 0; ++pi) {
+        const Preset& q = kPresets[pi];
+        if (q.lattice != P.lattice || q.tx != P.T[0] || q.ty != P.T[1] || q.tz != P.T[2]) continue;
+        if (P.LP > preset_LP(q) || P.WY > preset_WY(q) || P.WZ > preset_WZ(q)) continue;
+        bool uniform = true;
+        for (const Replica& R : P.reps)
+            for (int a = 0; a < 3; ++a)
+                for (int e : R.edges[a]) uniform &= e == q.ell;
+        if (!uniform || P.K > 5 || P.nbuf != 1) continue;
+        P.preset = pi;
+        P.LP = preset_LP(q);
+        P.WY = preset_WY(q);
+        P.WZ = preset_WZ(q);
+    }
     if (P.LP > 4096) return fail(SMCX_E_UNSUPPORTED, "tile window rows longer than 4096 bytes; use a smaller tile");
     const int64_t win = (int64_t)P.LP * P.WY * P.WZ;
     if (win > 160 * 1024) return fail(SMCX_E_UNSUPPORTED, "tile window does not fit in LDS; use a smaller tile");
-    P.lds = lds_layout(P.lattice, P.K, P.S, P.Z1, P.sumZ, (int)win);
+    P.lds = lds_layout(P.lattice, P.K, P.S, P.Z1, P.sumZ, (int)win, P.nbuf);
     if (P.lds.total > 160 * 1024) return fail(SMCX_E_UNSUPPORTED, "tile window and tables exceed 160 KiB of LDS");
     const int64_t max_off = 2LL * P.LP * P.WY + 2LL * P.LP + 2 * P.m + 4;
     if (max_off > 32767) return fail(SMCX_E_UNSUPPORTED, "LDS offsets exceed 16 bits; use a smaller tile");
@@ -262,6 +283,8 @@ struct smcx_lattice {
     std::vector<hipEvent_t> pool;
     int64_t timed_launches = 0;
     int stream_wgs = 8;  // stream-mode grid: 8 XCD chunks x workgroups per XCD
+    const void* k_stream = nullptr;
+    const void* k_persistent = nullptr;
 };
 
 namespace {
@@ -293,6 +316,7 @@ SweepArgs base_args(smcx_lattice* h)
     a.lds_pd = P.lds.pd_off;
     a.lds_win = P.lds.win_off;
     a.win_bytes = P.lds.win_bytes;
+    a.nbuf = P.nbuf;
     a.only_rep = -1;
     a.sweep_counter = nullptr;
     return a;
@@ -319,7 +343,7 @@ int timed_launch(smcx_lattice* h, bool persistent, dim3 grid, hipStream_t st, co
         if (!e0 || !e1) return fail(SMCX_E_HIP, "hipEventCreate failed");
         SMCX_HIP(hipEventRecord(e0, st));
     }
-    SMCX_HIP(launch_sweep(h->P.lattice, h->P.K, persistent, grid, h->P.block, h->P.lds.total, st, a));
+    SMCX_HIP(launch_sweep(persistent ? h->k_persistent : h->k_stream, grid, h->P.block, h->P.lds.total, st, a));
     if (h->timing) {
         SMCX_HIP(hipEventRecord(e1, st));
         h->pending.emplace_back(e0, e1);
@@ -457,12 +481,19 @@ int smcx_lattice_init(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_de
         delete h;
         return fail(SMCX_E_INVALID_ARG, "occupancy holds a species >= n_species");
     }
-    SMCX_HIP(set_sweep_lds_limit(P.lattice, P.K, P.lds.total));
+    h->k_stream = sweep_kernel(P.lattice, P.K, false, P.preset, P.nbuf);
+    h->k_persistent = sweep_kernel(P.lattice, P.K, true, -1, 1);
+    if (!h->k_stream || !h->k_persistent) {
+        delete h;
+        return fail(SMCX_E_UNSUPPORTED, "no sweep kernel for this configuration");
+    }
+    SMCX_HIP(set_sweep_lds_limit(h->k_stream, P.lds.total));
+    SMCX_HIP(set_sweep_lds_limit(h->k_persistent, P.lds.total));
     // stream grid: every CU filled to the occupancy the LDS footprint allows
     int dev = 0, cus = 256, per_cu = 1;
     SMCX_HIP(hipGetDevice(&dev));
     SMCX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    SMCX_HIP(ministep_occupancy(P.lattice, P.K, P.block, P.lds.total, &per_cu));
+    SMCX_HIP(sweep_occupancy(h->k_stream, P.block, P.lds.total, &per_cu));
     h->stream_wgs = 8 * std::max(1, (cus / 8) * std::max(1, per_cu));
     *out = h;
     g_err.clear();
@@ -750,7 +781,7 @@ int smcx_ladder_capture(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, const 
     a.tau_end = P.max_nA;
     int rc = pack_all(h, false, st);
     hipError_t e = hipSuccess;
-    if (rc == SMCX_OK) e = launch_sweep(P.lattice, P.K, true, dim3(P.R), P.block, P.lds.total, st, a);
+    if (rc == SMCX_OK) e = launch_sweep(h->k_persistent, dim3(P.R), P.block, P.lds.total, st, a);
     if (rc == SMCX_OK && e == hipSuccess) e = launch_advance_counter(sweep_counter_dev, (uint32_t)n_sweeps, st);
     if (rc == SMCX_OK && e == hipSuccess) rc = pack_all(h, true, st);
     hipGraph_t graph = nullptr;

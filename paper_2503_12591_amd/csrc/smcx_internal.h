@@ -148,6 +148,42 @@ struct RepDev {
     uint8_t mult[kMaxShells][kMaxZ1];  // images of the partner inside each shell
 };
 
+// ---------------------------------------------------------------------------
+// Compile-time window presets for uniform partitions (every link cell of edge
+// ELL).  A tile of TX x TY x TZ cells starting at cell c0 and mini-step
+// offsets o stages conventional cells c0*ELL + o - H .. + ELL*(T-1) + 2H on
+// each axis; along x the staged bytes are 16-byte aligned, which for
+// TX*ELL*m divisible by 16 starts at floor16(m*o) past the tile origin.
+// ---------------------------------------------------------------------------
+struct Preset {
+    int lattice, tx, ty, tz, ell;
+};
+
+constexpr Preset kPresets[] = {
+    {SMCX_BCC, 16, 4, 4, 4},
+    {SMCX_BCC, 16, 4, 2, 4},
+    {SMCX_FCC, 16, 4, 2, 4},
+    {SMCX_FCC, 8, 4, 4, 4},
+};
+constexpr int kNumPresets = sizeof(kPresets) / sizeof(kPresets[0]);
+
+constexpr int preset_m(const Preset& p) { return p.lattice == SMCX_BCC ? 2 : 4; }
+constexpr int preset_w(int t, int ell) { return ell * (t - 1) + 1 + 2 * kHalo; }
+constexpr int preset_LP(const Preset& p)
+{
+    const int m = preset_m(p);
+    int best = 0;
+    for (int o = 0; o < p.ell; ++o) {
+        const int lo = (m * o) & ~15;
+        const int hi = (m * (o + preset_w(p.tx, p.ell)) + 15) & ~15;
+        if (hi - lo > best) best = hi - lo;
+    }
+    return best;
+}
+constexpr int preset_WY(const Preset& p) { return preset_w(p.ty, p.ell); }
+constexpr int preset_WZ(const Preset& p) { return preset_w(p.tz, p.ell); }
+constexpr bool preset_ok(const Preset& p) { return (p.tx * p.ell * preset_m(p)) % 16 == 0; }
+
 // Arguments of the sweep kernels (passed by value).
 struct SweepArgs {
     const RepDev* reps;
@@ -172,7 +208,8 @@ struct SweepArgs {
     int32_t T[3];              // tile shape (link cells)
     int32_t LP, WY, WZ;        // LDS window: row pitch, rows per plane, planes
     int32_t lds_d, lds_offp, lds_offb, lds_pd, lds_win;  // dynamic-LDS byte offsets
-    int32_t win_bytes;         // one window buffer (two are used, back to back)
+    int32_t win_bytes;         // one window buffer
+    int32_t nbuf;              // window buffers: 2 = next tile streams in during the trials, 1 = staged in turn
     int32_t g;                 // mini-step (stream / plain launches)
     int32_t tau_begin, tau_end; // persistent launches: mini-step range of every sweep
     int32_t only_rep;          // plain launches: the replica, else -1
@@ -183,7 +220,7 @@ struct LdsLayout {
     int d_off, offp_off, offb_off, pd_off, win_off, win_bytes, total;
 };
 
-inline LdsLayout lds_layout(int lattice, int K, int S, int Z1, int sumZ, int win_bytes)
+inline LdsLayout lds_layout(int lattice, int K, int S, int Z1, int sumZ, int win_bytes, int nbuf)
 {
     auto al = [](int v) { return (v + 15) & ~15; };
     const int m = lattice == SMCX_BCC ? 2 : 4;
@@ -195,7 +232,7 @@ inline LdsLayout lds_layout(int lattice, int K, int S, int Z1, int sumZ, int win
     L.pd_off = o;   o = al(o + 4 * m * Z1);
     L.win_off = o;
     L.win_bytes = al(win_bytes);
-    o = al(o + 2 * L.win_bytes);  // two window buffers
+    o = al(o + nbuf * L.win_bytes);
     L.total = o;
     return L;
 }

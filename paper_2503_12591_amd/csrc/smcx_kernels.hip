@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "smcx_internal.h"
 #include "smcx_launch.h"
 
@@ -84,6 +86,12 @@ __device__ __forceinline__ int species_of(int v, int F) { return F == 8 ? v >> 3
 __device__ __forceinline__ void store_site(uint8_t* pad, const RepDev& rep, int m, int x, int y, int z,
                                            int b, uint8_t v)
 {
+    if (x >= kHalo && x < rep.L[0] - kHalo && y >= kHalo && y < rep.L[1] - kHalo && z >= kHalo &&
+        z < rep.L[2] - kHalo) {
+        // away from the faces a site has no other image
+        pad[((int64_t)(z + kHalo) * rep.prows + (y + kHalo)) * rep.prow + m * (x + kHalo) + b] = v;
+        return;
+    }
     int xs[3], ys[3], zs[3];
     int nx = 0, ny = 0, nz = 0;
     xs[nx++] = x;
@@ -116,11 +124,16 @@ __device__ __forceinline__ uint64_t shl1_add(uint32_t sh, uint64_t acc) { return
 // Packed neighbour counters of a basis-B site at LDS byte `base`: A[s] gets
 // 1 << (8 * species) per neighbour of shell s.  Offsets are compile-time
 // displacements times the launch-uniform window pitches.
+// The reads are rebased at the most negative offset (a window's neighbours lie
+// within two conventional cells on every axis), so that every per-neighbour
+// offset is a non-negative constant that fits the LDS instruction's immediate.
 template <int LAT, int B, typename CT>
 __device__ __forceinline__ void count_uniform(const uint8_t* win, int base, int LP, int PL, int S,
                                               CT (&A)[kMaxShells])
 {
     constexpr Geometry G = kGeom[LAT];
+    const int lo = -kHalo * PL - kHalo * LP - G.m * kHalo - (G.m - 1);
+    const uint8_t* w = win + (base + lo);
 #pragma unroll
     for (int s = 0; s < kMaxShells; ++s) {
         CT acc = 0;
@@ -129,7 +142,7 @@ __device__ __forceinline__ void count_uniform(const uint8_t* win, int base, int 
             for (int n = 0; n < G.Z[s]; ++n) {
                 const Nb nb = nb_of(G, B, G.v[s][n][0], G.v[s][n][1], G.v[s][n][2]);
                 const int off = nb.dz * PL + nb.dy * LP + G.m * nb.dx + (nb.bt - B);
-                acc = shl1_add(win[base + off], acc);
+                acc = shl1_add(w[off - lo], acc);
             }
         }
         A[s] = acc;
@@ -192,43 +205,91 @@ __device__ void load_tables(const SweepArgs& A, uint8_t* smem)
     for (int i = threadIdx.x; i < 4 * m * A.Z1; i += blockDim.x) pd[i] = A.pdisp[i];
 }
 
+// ---------------------------------------------------------------------------
+// Window geometry policies.  GeoRt reads tile shape and window pitches from
+// the launch arguments (any partition); GeoFix<...> fixes them at compile
+// time for uniform partitions, so that every LDS neighbour offset is an
+// immediate and cell origins are c * ELL.
+// ---------------------------------------------------------------------------
+struct GeoRt {
+    static constexpr bool fixed = false;
+    static constexpr int ELL = 0;
+    __device__ static int T(const SweepArgs& A, int a) { return A.T[a]; }
+    __device__ static int LP(const SweepArgs& A) { return A.LP; }
+    __device__ static int WY(const SweepArgs& A) { return A.WY; }
+    __device__ static int WZ(const SweepArgs& A) { return A.WZ; }
+    __device__ static int block(const SweepArgs&) { return blockDim.x; }
+};
+
+template <int PI>
+struct GeoFix {
+    static constexpr Preset P = kPresets[PI];
+    static_assert(preset_ok(P), "tile start must be 16-byte aligned");
+    static constexpr bool fixed = true;
+    static constexpr int ELL = P.ell;
+    static constexpr int kLP = preset_LP(P), kWY = preset_WY(P), kWZ = preset_WZ(P);
+    static constexpr int kBLOCK = (P.tx * P.ty * P.tz + 63) / 64 * 64;
+    __device__ static constexpr int T(const SweepArgs&, int a) { return a == 0 ? P.tx : (a == 1 ? P.ty : P.tz); }
+    __device__ static constexpr int LP(const SweepArgs&) { return preset_LP(P); }
+    __device__ static constexpr int WY(const SweepArgs&) { return preset_WY(P); }
+    __device__ static constexpr int WZ(const SweepArgs&) { return preset_WZ(P); }
+    __device__ static constexpr int block(const SweepArgs&) { return (P.tx * P.ty * P.tz + 63) / 64 * 64; }
+};
+
 struct TileGeom {
     int w0[3];   // window origin (replica conventional cells, >= -H)
     int n[3];    // window extent
     int gx0;     // first staged byte of each padded row
     int c0[3];   // first link cell of the tile
     int c1[3];   // one past the last link cell
-    int n16;     // staged 16-byte chunks per row
 };
 
-// Window of one tile for mini-step offsets o: identical in every thread.
+template <class Geo>
+__device__ __forceinline__ int cell_origin(const SweepArgs& A, const RepDev& rep, int a, int c)
+{
+    if constexpr (Geo::fixed) {
+        return c * Geo::ELL;
+    } else {
+        const int32_t* org = A.origins + rep.cs_off;
+        if (a > 0) org += rep.nc[0] + 1;
+        if (a > 1) org += rep.nc[1] + 1;
+        return org[c];
+    }
+}
+
+// Window of one tile for mini-step offsets o, identical in every thread.
 // Returns false when no cell of the tile has these offsets.
-template <int LAT>
+template <int LAT, class Geo>
 __device__ __forceinline__ bool tile_geometry(const SweepArgs& A, const RepDev& rep, int64_t tile,
                                               const int (&o)[3], TileGeom& tg)
 {
     constexpr int m = kGeom[LAT].m;
-    const int tx = (int)(tile % rep.ntile[0]);
-    const int64_t trest = tile / rep.ntile[0];
-    const int ty = (int)(trest % rep.ntile[1]);
-    const int tz = (int)(trest / rep.ntile[1]);
-    tg.c0[0] = tx * A.T[0];
-    tg.c0[1] = ty * A.T[1];
-    tg.c0[2] = tz * A.T[2];
-    const int32_t* org = A.origins + rep.cs_off;
+    // tiles per replica stay below 2^31 (cells per replica do), so 32-bit division
+    const int tl = (int)tile;
+    const int tx = tl % rep.ntile[0];
+    const int trest = tl / rep.ntile[0];
+    const int ty = trest % rep.ntile[1];
+    const int tz = trest / rep.ntile[1];
+    tg.c0[0] = tx * Geo::T(A, 0);
+    tg.c0[1] = ty * Geo::T(A, 1);
+    tg.c0[2] = tz * Geo::T(A, 2);
     bool any = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        tg.c1[a] = min(tg.c0[a] + A.T[a], rep.nc[a]);
-        tg.w0[a] = org[tg.c0[a]] + o[a] - kHalo;
-        const int w1 = min(org[tg.c1[a] - 1] + o[a] + kHalo + 1, rep.L[a] + kHalo);
+        tg.c1[a] = min(tg.c0[a] + Geo::T(A, a), rep.nc[a]);
+        tg.w0[a] = cell_origin<Geo>(A, rep, a, tg.c0[a]) + o[a] - kHalo;
+        const int w1 = min(cell_origin<Geo>(A, rep, a, tg.c1[a] - 1) + o[a] + kHalo + 1, rep.L[a] + kHalo);
         tg.n[a] = w1 - tg.w0[a];
         any &= tg.n[a] > 0;
-        org += rep.nc[a] + 1;
+        if constexpr (!Geo::fixed) {
+            // some cell of the tile must be longer than the offset (uneven partitions)
+            bool has = false;
+            for (int c = tg.c0[a]; c < tg.c1[a]; ++c)
+                has |= cell_origin<Geo>(A, rep, a, c + 1) - cell_origin<Geo>(A, rep, a, c) > o[a];
+            any &= has;
+        }
     }
     tg.gx0 = (m * (tg.w0[0] + kHalo)) & ~15;
-    const int gx1 = (m * (tg.w0[0] + tg.n[0] + kHalo) + 15) & ~15;
-    tg.n16 = (gx1 - tg.gx0) >> 4;
     return any;
 }
 
@@ -237,22 +298,27 @@ __device__ __forceinline__ bool tile_geometry(const SweepArgs& A, const RepDev& 
 // bytes at buf + 16 j) is row R = j / LPc, chunk j % LPc; row R holds window
 // plane R / WY, row R % WY.  The loads complete asynchronously; the caller
 // waits on vmcnt and a barrier before reading the buffer.
+template <int LAT, class Geo>
 __device__ __forceinline__ void stage_async(const SweepArgs& A, const RepDev& rep, const TileGeom& tg,
                                             const uint8_t* pad, uint8_t* buf)
 {
-    const int LPc = A.LP >> 4;
-    const int nslots = A.WZ * A.WY * LPc;
+    constexpr int m = kGeom[LAT].m;
+    const int LPc = Geo::LP(A) >> 4;
+    const int WY = Geo::WY(A);
+    const int nslots = Geo::WZ(A) * WY * LPc;
+    const int gx1 = (m * (tg.w0[0] + tg.n[0] + kHalo) + 15) & ~15;
+    const int n16 = (gx1 - tg.gx0) >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int step = blockDim.x;
+    const int step = Geo::block(A);
     int j = wave * 64 + lane;
     int R = j / LPc, col = j - R * LPc;
-    int wz = R / A.WY, wy = R - wz * A.WY;
+    int wz = R / WY, wy = R - wz * WY;
     const int dR = step / LPc, dcol = step - dR * LPc;
     const uint8_t* base = pad + ((int64_t)(tg.w0[2] + kHalo) * rep.prows + (tg.w0[1] + kHalo)) * rep.prow + tg.gx0;
     const int64_t plane = (int64_t)rep.prows * rep.prow;
     for (int jb = wave * 64; jb < nslots; jb += step) {
-        if (jb + lane < nslots && col < tg.n16 && wy < tg.n[1] && wz < tg.n[2]) {
+        if (jb + lane < nslots && col < n16 && wy < tg.n[1] && wz < tg.n[2]) {
             const uint8_t* src = base + wz * plane + (int64_t)wy * rep.prow + 16 * col;
             __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
                                              (__attribute__((address_space(3))) void*)(buf + 16 * jb), 16, 0, 0);
@@ -263,26 +329,67 @@ __device__ __forceinline__ void stage_async(const SweepArgs& A, const RepDev& re
             col -= LPc;
             ++wy;
         }
-        while (wy >= A.WY) {
-            wy -= A.WY;
+        while (wy >= WY) {
+            wy -= WY;
             ++wz;
         }
     }
 }
 
+// Per-thread staging plan of a compile-time window: thread t stages window
+// slots t + i * BLOCK; soff[i] is the slot's byte offset from the window's
+// first staged byte in the padded copy (plane and row pitches of a replica).
+template <int LAT, class Geo>
+struct StagePlan {
+    static constexpr int LPc = Geo::kLP / 16;
+    static constexpr int WY = Geo::kWY;
+    static constexpr int WZ = Geo::kWZ;
+    static constexpr int NSLOT = WZ * WY * LPc;
+    static constexpr int BLOCK = Geo::kBLOCK;
+    static constexpr int NP = (NSLOT + BLOCK - 1) / BLOCK;
+    int soff[NP];
+    int rep = -1;
+
+    __device__ __forceinline__ void prepare(const RepDev& rp, int r)
+    {
+        if (r == rep) return;
+        rep = r;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int slot = threadIdx.x + i * BLOCK;
+            const int R = slot / LPc, col = slot - R * LPc;
+            const int wz = R / WY, wy = R - wz * WY;
+            soff[i] = (wz * rp.prows + wy) * rp.prow + 16 * col;
+        }
+    }
+
+    // every slot of a full window lies inside the padded copy
+    __device__ __forceinline__ void stage_full(const uint8_t* first, uint8_t* buf) const
+    {
+        const int wave64 = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            if (i * BLOCK + wave64 < NSLOT && threadIdx.x + i * BLOCK < NSLOT)
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(first + soff[i]),
+                                                 (__attribute__((address_space(3))) void*)(buf + 16 * (i * BLOCK + wave64)),
+                                                 16, 0, 0);
+        }
+    }
+};
+
 // One lane's trial on the staged window `win`.  Returns flags: bit0 active,
 // bit1 accepted, bit2 near-tie.
-template <int LAT, int NW, int B>
-__device__ __forceinline__ int lane_trial(const SweepArgs& A, const RepDev& rep, uint8_t* pad,
-                                          const Lds& T, const uint8_t* win, const TileGeom& tg, int r,
-                                          uint32_t t, double beta, int ax, int ay, int az)
+template <int LAT, int E, int B, class Geo>
+__device__ __forceinline__ int lane_trial(const SweepArgs& A, const RepDev& rep, uint8_t* pad, const Lds& T,
+                                          const uint8_t* win, const TileGeom& tg, int r, uint32_t t, double beta,
+                                          int ax, int ay, int az)
 {
-    using EN = Enc<NW>;
+    using EN = Enc<E>;
     using CT = typename EN::T;
     constexpr Geometry G = kGeom[LAT];
     constexpr int m = G.m;
-    const int LP = A.LP, PL = A.LP * A.WY;
-    const int la = ((az - tg.w0[2]) * A.WY + (ay - tg.w0[1])) * LP + (m * (ax + kHalo) + B - tg.gx0);
+    const int LP = Geo::LP(A), WY = Geo::WY(A), PL = LP * WY;
+    const int la = ((az - tg.w0[2]) * WY + (ay - tg.w0[1])) * LP + (m * (ax + kHalo) + B - tg.gx0);
     const int64_t ia = B + (int64_t)m * (ax + (int64_t)rep.L[0] * (ay + (int64_t)rep.L[1] * az));
 
     uint32_t w0, w1, w2, w3;
@@ -307,7 +414,6 @@ __device__ __forceinline__ int lane_trial(const SweepArgs& A, const RepDev& rep,
     // species were checked < K at init; the clamp keeps table reads in bounds regardless
     const int p = min(species_of(p8, EN::F), A.K - 1), q = min(species_of(q8, EN::F), A.K - 1);
     const double* Dp = T.D + (size_t)((p * A.K + q) * A.S) * A.K;
-    constexpr int KP = EN::KP;
     double dE = 0.0;
 #pragma unroll
     for (int s = 0; s < kMaxShells; ++s) {
@@ -316,7 +422,7 @@ __device__ __forceinline__ int lane_trial(const SweepArgs& A, const RepDev& rep,
             const CT mu = rep.alias ? (CT)rep.mult[s][k] : (CT)(s == 0 ? 1 : 0);
             const CT d = Ca[s] + EN::bias - Cb[s] + (mu << p8) - (mu << q8);
 #pragma unroll
-            for (int tt = 0; tt < KP; ++tt) {
+            for (int tt = 0; tt < EN::KP; ++tt) {
                 if (tt < A.K) {
                     const int c = (int)((d >> (EN::F * tt)) & EN::mask) - EN::half;
                     dE = dE + (double)c * Dp[s * A.K + tt];
@@ -355,27 +461,27 @@ __device__ __forceinline__ int lane_trial(const SweepArgs& A, const RepDev& rep,
         bx += bx < 0 ? rep.L[0] : (bx >= rep.L[0] ? -rep.L[0] : 0);
         by += by < 0 ? rep.L[1] : (by >= rep.L[1] ? -rep.L[1] : 0);
         bz += bz < 0 ? rep.L[2] : (bz >= rep.L[2] ? -rep.L[2] : 0);
-        // the padded copy holds 8 * species, like the window
+        // the padded copy holds F * species, like the window
         store_site(pad, rep, m, ax, ay, az, B, (uint8_t)q8);
         store_site(pad, rep, m, bx, by, bz, bb, (uint8_t)p8);
     }
     return 1 | (acc ? 2 : 0) | (tie ? 4 : 0);
 }
 
-template <int LAT, int NW>
+template <int LAT, int E, class Geo>
 __device__ __forceinline__ int lane_dispatch(int b, const SweepArgs& A, const RepDev& rep, uint8_t* pad,
                                              const Lds& T, const uint8_t* win, const TileGeom& tg, int r,
                                              uint32_t t, double beta, int ax, int ay, int az)
 {
     if constexpr (LAT == SMCX_BCC) {
-        if (b == 0) return lane_trial<LAT, NW, 0>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
-        return lane_trial<LAT, NW, 1>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
+        if (b == 0) return lane_trial<LAT, E, 0, Geo>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
+        return lane_trial<LAT, E, 1, Geo>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
     } else {
         switch (b) {
-        case 0: return lane_trial<LAT, NW, 0>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
-        case 1: return lane_trial<LAT, NW, 1>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
-        case 2: return lane_trial<LAT, NW, 2>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
-        default: return lane_trial<LAT, NW, 3>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
+        case 0: return lane_trial<LAT, E, 0, Geo>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
+        case 1: return lane_trial<LAT, E, 1, Geo>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
+        case 2: return lane_trial<LAT, E, 2, Geo>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
+        default: return lane_trial<LAT, E, 3, Geo>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
         }
     }
 }
@@ -405,47 +511,56 @@ __device__ __forceinline__ void flush_stats(const SweepArgs& A, int r, Stats& st
     st = Stats();
 }
 
-// Trials of the lanes of one staged tile.
-template <int LAT, int NW>
+// Block barrier that orders LDS accesses only: global loads issued before it
+// stay in flight (a full __syncthreads also drains them).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Trials of the lanes of one staged tile (one lane per link cell).
+template <int LAT, int E, class Geo>
 __device__ __forceinline__ void tile_trials(const SweepArgs& A, const RepDev& rep, int r, const TileGeom& tg,
                                             int b, const int (&o)[3], uint32_t t, double beta, const Lds& T,
                                             const uint8_t* win, Stats& st)
 {
     const int l = threadIdx.x;
-    const int lx = l % A.T[0];
-    const int ly = (l / A.T[0]) % A.T[1];
-    const int lz = l / (A.T[0] * A.T[1]);
+    const int lx = l % Geo::T(A, 0);
+    const int ly = (l / Geo::T(A, 0)) % Geo::T(A, 1);
+    const int lz = l / (Geo::T(A, 0) * Geo::T(A, 1));
     const int cx = tg.c0[0] + lx, cy = tg.c0[1] + ly, cz = tg.c0[2] + lz;
-    if (!(lz < A.T[2] && cx < tg.c1[0] && cy < tg.c1[1] && cz < tg.c1[2])) return;
-    const int32_t* ox = A.origins + rep.cs_off;
-    const int32_t* oy = ox + rep.nc[0] + 1;
-    const int32_t* oz = oy + rep.nc[1] + 1;
-    const int ax = ox[cx] + o[0], ay = oy[cy] + o[1], az = oz[cz] + o[2];
-    if (!(ax < ox[cx + 1] && ay < oy[cy + 1] && az < oz[cz + 1])) return;
+    if (!(lz < Geo::T(A, 2) && cx < tg.c1[0] && cy < tg.c1[1] && cz < tg.c1[2])) return;
+    const int ax = cell_origin<Geo>(A, rep, 0, cx) + o[0];
+    const int ay = cell_origin<Geo>(A, rep, 1, cy) + o[1];
+    const int az = cell_origin<Geo>(A, rep, 2, cz) + o[2];
+    if constexpr (!Geo::fixed) {
+        if (!(ax < cell_origin<Geo>(A, rep, 0, cx + 1) && ay < cell_origin<Geo>(A, rep, 1, cy + 1) &&
+              az < cell_origin<Geo>(A, rep, 2, cz + 1)))
+            return;
+    }
     uint8_t* pad = A.ws + rep.pad_off;
-    const int f = lane_dispatch<LAT, NW>(b, A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
+    const int f = lane_dispatch<LAT, E, Geo>(b, A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
     st.att += 1;
     st.acc += (f >> 1) & 1;
     st.tie += (f >> 2) & 1;
 }
 
 // Tiles first, first + step, ... (< end) of a logical tile space for mini-step
-// tau of sweep t, window loads double-buffered: the next tile's window streams
-// into LDS while the current tile's trials run.  tile_of(i, r, tile) maps a
-// logical index to (replica, tile of that replica); beta_of(r) gives the
-// replica's inverse temperature.  Every thread calls this with the same
-// arguments; it ends with all of its global writes issued.
-template <int LAT, int NW, typename TileOf, typename BetaOf>
-__device__ void run_tiles(const SweepArgs& A, int64_t first, int64_t end, int64_t step, int tau_fixed,
-                          uint32_t t, const Lds& T, uint8_t* win0, uint8_t* win1, TileOf tile_of, BetaOf beta_of,
-                          Stats& st, int& r_stats)
+// tau of sweep t.  With two window buffers the next tile's window streams into
+// LDS while the current tile's trials run; with one, each window is staged in
+// turn (half the LDS, so more workgroups per CU hide the latency instead).
+// tile_of(i, r, tile) maps a logical index to (replica, tile of that replica);
+// beta_of(r) gives the replica's inverse temperature.  Every thread calls this
+// with the same arguments.
+template <int LAT, int E, class Geo, int NBUF, typename TileOf, typename BetaOf>
+__device__ void run_tiles(const SweepArgs& A, int64_t first, int64_t end, int64_t step, int tau, uint32_t t,
+                          const Lds& T, uint8_t* win0, uint8_t* win1, TileOf tile_of, BetaOf beta_of, Stats& st,
+                          int& r_stats)
 {
     constexpr int m = kGeom[LAT].m;
     if (first >= end) return;
-    int r, rn;
-    int64_t tile, tilen;
-    tile_of(first, r, tile);
-    int tau = tau_fixed;
     auto offsets = [&](const RepDev& rep, int (&o)[3], int& b) {
         b = tau % m;
         const int rest = tau / m;
@@ -453,44 +568,96 @@ __device__ void run_tiles(const SweepArgs& A, int64_t first, int64_t end, int64_
         o[1] = (rest / rep.M[0]) % rep.M[1];
         o[2] = rest / (rep.M[0] * rep.M[1]);
     };
+    if constexpr (NBUF == 1) {
+        struct NoPlan {};
+        [[maybe_unused]] std::conditional_t<Geo::fixed, StagePlan<LAT, Geo>, NoPlan> plan;
+        for (int64_t i = first; i < end; i += step) {
+            int r;
+            int64_t tile;
+            tile_of(i, r, tile);
+            const RepDev& rep = A.reps[r];
+            if (tau >= rep.nA) continue;  // uniform across the block
+            int o[3], b;
+            offsets(rep, o, b);
+            TileGeom tg;
+            if (!tile_geometry<LAT, Geo>(A, rep, tile, o, tg)) continue;
+            lds_barrier();  // every lane is done with the window of the previous tile
+            const uint8_t* pad = A.ws + rep.pad_off;
+            if constexpr (Geo::fixed) {
+                constexpr int m = kGeom[LAT].m;
+                using SP = decltype(plan);
+                const int gx1 = (m * (tg.w0[0] + tg.n[0] + kHalo) + 15) & ~15;
+                if (((gx1 - tg.gx0) >> 4) == SP::LPc && tg.n[1] == SP::WY && tg.n[2] == SP::WZ) {
+                    plan.prepare(rep, r);
+                    plan.stage_full(pad + ((int64_t)(tg.w0[2] + kHalo) * rep.prows + (tg.w0[1] + kHalo)) * rep.prow +
+                                        tg.gx0,
+                                    win0);
+                } else {
+                    stage_async<LAT, Geo>(A, rep, tg, pad, win0);
+                }
+            } else {
+                stage_async<LAT, Geo>(A, rep, tg, pad, win0);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (r != r_stats) {
+                flush_stats(A, r_stats, st);
+                r_stats = r;
+            }
+            tile_trials<LAT, E, Geo>(A, rep, r, tg, b, o, t, beta_of(r), T, win0, st);
+        }
+        return;
+    }
+    int r = 0, rn = 0;
+    int64_t tile = 0, tilen = 0;
+    tile_of(first, r, tile);
     int o[3], b;
     TileGeom tg;
-    bool have = false;
+    bool have;
+    constexpr bool dbl = true;
     {
         const RepDev& rep = A.reps[r];
         offsets(rep, o, b);
-        have = tau < rep.nA && tile_geometry<LAT>(A, rep, tile, o, tg);
-        if (have) stage_async(A, rep, tg, A.ws + rep.pad_off, win0);
+        have = tau < rep.nA && tile_geometry<LAT, Geo>(A, rep, tile, o, tg);
+        if (have && dbl) stage_async<LAT, Geo>(A, rep, tg, A.ws + rep.pad_off, win0);
     }
     int k = 0;
     for (int64_t i = first; i < end; i += step, ++k) {
         const int64_t inext = i + step;
-        int on[3], bn;
+        int on[3] = {0, 0, 0}, bn = 0;
         TileGeom tgn;
         bool haven = false;
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();  // window of tile i landed; all lanes done with the other buffer
-        uint8_t* cur = (k & 1) ? win1 : win0;
-        uint8_t* nxt = (k & 1) ? win0 : win1;
         if (inext < end) {
             tile_of(inext, rn, tilen);
             const RepDev& repn = A.reps[rn];
             offsets(repn, on, bn);
-            haven = tau < repn.nA && tile_geometry<LAT>(A, repn, tilen, on, tgn);
-            if (haven) stage_async(A, repn, tgn, A.ws + repn.pad_off, nxt);
+            haven = tau < repn.nA && tile_geometry<LAT, Geo>(A, repn, tilen, on, tgn);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();  // double buffering: window of tile i landed; both: lanes done with the buffer
+        uint8_t* cur = win0;
+        if (dbl) {
+            cur = (k & 1) ? win1 : win0;
+            if (haven) stage_async<LAT, Geo>(A, A.reps[rn], tgn, A.ws + A.reps[rn].pad_off, (k & 1) ? win0 : win1);
+        } else if (have) {
+            stage_async<LAT, Geo>(A, A.reps[r], tg, A.ws + A.reps[r].pad_off, win0);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
         }
         if (have) {
             if (r != r_stats) {
                 flush_stats(A, r_stats, st);
                 r_stats = r;
             }
-            tile_trials<LAT, NW>(A, A.reps[r], r, tg, b, o, t, beta_of(r), T, cur, st);
+            tile_trials<LAT, E, Geo>(A, A.reps[r], r, tg, b, o, t, beta_of(r), T, cur, st);
         }
         r = rn;
         tile = tilen;
         tg = tgn;
         have = haven;
-        o[0] = on[0]; o[1] = on[1]; o[2] = on[2];
+        o[0] = on[0];
+        o[1] = on[1];
+        o[2] = on[2];
         b = bn;
     }
 }
@@ -502,7 +669,7 @@ __device__ void run_tiles(const SweepArgs& A, int64_t first, int64_t end, int64_
 // walk their chunk together with stride W, so neighbouring tiles -- which
 // share halo rows -- are in flight on the same L2 at the same time.
 // ---------------------------------------------------------------------------
-template <int LAT, int NW>
+template <int LAT, int E, class Geo, int NBUF>
 __global__ __launch_bounds__(kBlock) void k_ministep(SweepArgs A)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -531,8 +698,8 @@ __global__ __launch_bounds__(kBlock) void k_ministep(SweepArgs A)
     auto beta_of = [&](int r) { return A.beta[r]; };
     Stats st;
     int r_stats = -1;
-    run_tiles<LAT, NW>(A, lo + blockIdx.x / 8, hi, W, A.g, A.first_sweep, T, smem + A.lds_win,
-                       smem + A.lds_win + A.win_bytes, tile_of, beta_of, st, r_stats);
+    run_tiles<LAT, E, Geo, NBUF>(A, lo + blockIdx.x / 8, hi, W, A.g, A.first_sweep, T, smem + A.lds_win,
+                           smem + A.lds_win + A.win_bytes, tile_of, beta_of, st, r_stats);
     flush_stats(A, r_stats, st);
 }
 
@@ -541,7 +708,7 @@ __global__ __launch_bounds__(kBlock) void k_ministep(SweepArgs A)
 // block barriers order the mini-steps (all writes of a replica come from its
 // own workgroup, and a barrier makes them visible to its later loads).
 // ---------------------------------------------------------------------------
-template <int LAT, int NW>
+template <int LAT, int E, class Geo>
 __global__ __launch_bounds__(kBlock) void k_persistent(SweepArgs A)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -564,8 +731,8 @@ __global__ __launch_bounds__(kBlock) void k_persistent(SweepArgs A)
         for (int tau = A.tau_begin; tau < tau_end; ++tau) {
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();  // the previous mini-step's writes are visible to every wave
-            run_tiles<LAT, NW>(A, 0, rep.ntiles, 1, tau, t, T, smem + A.lds_win, smem + A.lds_win + A.win_bytes,
-                               tile_of, beta_of, st, r_stats);
+            run_tiles<LAT, E, Geo, 1>(A, 0, rep.ntiles, 1, tau, t, T, smem + A.lds_win,
+                                   smem + A.lds_win + A.win_bytes, tile_of, beta_of, st, r_stats);
         }
     }
     flush_stats(A, r_stats, st);
@@ -729,70 +896,65 @@ __global__ __launch_bounds__(kBlock) void k_pair_counts(const uint8_t* occ, int6
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
-template <int LAT, int NW>
-static hipError_t launch_sweep_t(bool persistent, dim3 grid, int block, size_t lds, hipStream_t st,
-                                 const SweepArgs& a)
-{
-    if (persistent) {
-        hipLaunchKernelGGL((k_persistent<LAT, NW>), grid, dim3(block), lds, st, a);
-    } else {
-        hipLaunchKernelGGL((k_ministep<LAT, NW>), grid, dim3(block), lds, st, a);
-    }
-    return hipGetLastError();
-}
-
+// ---------------------------------------------------------------------------
+// Kernel resolution: (lattice, counter encoding, window preset) -> kernels.
+// Stream kernels exist for the runtime geometry and every preset of the
+// lattice; persistent kernels use the runtime geometry only.
+// ---------------------------------------------------------------------------
 int encoding_of(int K) { return K <= 4 ? 1 : (K == 5 ? 3 : 2); }
 int field_bits_of(int K) { return K == 5 ? 6 : 8; }
 
-hipError_t launch_sweep(int lattice, int K, bool persistent, dim3 grid, int block, size_t lds, hipStream_t st,
-                        const SweepArgs& a)
+template <int LAT, int E>
+static const void* stream_kernel(int preset, int nbuf)
 {
-    const int e = encoding_of(K);
-    if (lattice == SMCX_BCC) {
-        if (e == 1) return launch_sweep_t<SMCX_BCC, 1>(persistent, grid, block, lds, st, a);
-        if (e == 3) return launch_sweep_t<SMCX_BCC, 3>(persistent, grid, block, lds, st, a);
-        return launch_sweep_t<SMCX_BCC, 2>(persistent, grid, block, lds, st, a);
+    if constexpr (E != 2) {
+        if constexpr (LAT == SMCX_BCC) {
+            if (preset == 0) return (const void*)k_ministep<LAT, E, GeoFix<0>, 1>;
+            if (preset == 1) return (const void*)k_ministep<LAT, E, GeoFix<1>, 1>;
+        } else {
+            if (preset == 2) return (const void*)k_ministep<LAT, E, GeoFix<2>, 1>;
+            if (preset == 3) return (const void*)k_ministep<LAT, E, GeoFix<3>, 1>;
+        }
     }
-    if (e == 1) return launch_sweep_t<SMCX_FCC, 1>(persistent, grid, block, lds, st, a);
-    if (e == 3) return launch_sweep_t<SMCX_FCC, 3>(persistent, grid, block, lds, st, a);
-    return launch_sweep_t<SMCX_FCC, 2>(persistent, grid, block, lds, st, a);
+    if (preset >= 0) return nullptr;
+    if (nbuf == 2) return (const void*)k_ministep<LAT, E, GeoRt, 2>;
+    return (const void*)k_ministep<LAT, E, GeoRt, 1>;
 }
 
 template <int LAT, int E>
-static void sweep_kernels(const void*& f1, const void*& f2)
+static const void* persistent_kernel()
 {
-    f1 = (const void*)k_ministep<LAT, E>;
-    f2 = (const void*)k_persistent<LAT, E>;
+    return (const void*)k_persistent<LAT, E, GeoRt>;
 }
 
-static void sweep_kernels_for(int lattice, int K, const void*& f1, const void*& f2)
+
+const void* sweep_kernel(int lattice, int K, bool persistent, int preset, int nbuf)
 {
     const int e = encoding_of(K);
     if (lattice == SMCX_BCC) {
-        if (e == 1) sweep_kernels<SMCX_BCC, 1>(f1, f2);
-        else if (e == 3) sweep_kernels<SMCX_BCC, 3>(f1, f2);
-        else sweep_kernels<SMCX_BCC, 2>(f1, f2);
-    } else {
-        if (e == 1) sweep_kernels<SMCX_FCC, 1>(f1, f2);
-        else if (e == 3) sweep_kernels<SMCX_FCC, 3>(f1, f2);
-        else sweep_kernels<SMCX_FCC, 2>(f1, f2);
+        if (persistent) return e == 1 ? persistent_kernel<SMCX_BCC, 1>() : (e == 3 ? persistent_kernel<SMCX_BCC, 3>() : persistent_kernel<SMCX_BCC, 2>());
+        return e == 1 ? stream_kernel<SMCX_BCC, 1>(preset, nbuf) : (e == 3 ? stream_kernel<SMCX_BCC, 3>(preset, nbuf) : stream_kernel<SMCX_BCC, 2>(preset, nbuf));
     }
+    if (persistent) return e == 1 ? persistent_kernel<SMCX_FCC, 1>() : (e == 3 ? persistent_kernel<SMCX_FCC, 3>() : persistent_kernel<SMCX_FCC, 2>());
+    return e == 1 ? stream_kernel<SMCX_FCC, 1>(preset, nbuf) : (e == 3 ? stream_kernel<SMCX_FCC, 3>(preset, nbuf) : stream_kernel<SMCX_FCC, 2>(preset, nbuf));
 }
 
-hipError_t set_sweep_lds_limit(int lattice, int K, size_t lds)
+hipError_t launch_sweep(const void* kernel, dim3 grid, int block, size_t lds, hipStream_t st, const SweepArgs& a)
 {
-    const void *f1, *f2;
-    sweep_kernels_for(lattice, K, f1, f2);
-    hipError_t e = hipFuncSetAttribute(f1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(f2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (!kernel) return hipErrorInvalidDeviceFunction;
+    SweepArgs copy = a;
+    void* args[] = {&copy};
+    return hipLaunchKernel(kernel, grid, dim3(block), args, lds, st);
 }
 
-hipError_t ministep_occupancy(int lattice, int K, int block, size_t lds, int* blocks_per_cu)
+hipError_t set_sweep_lds_limit(const void* kernel, size_t lds)
 {
-    const void *f1, *f2;
-    sweep_kernels_for(lattice, K, f1, f2);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f1, block, lds);
+    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t sweep_occupancy(const void* kernel, int block, size_t lds, int* blocks_per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel, block, lds);
 }
 
 hipError_t launch_pack(int lattice, int K, bool unpack, uint8_t* occ, uint8_t* ws, const RepDev* reps, int r,
