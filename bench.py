@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--summarize", nargs="+", metavar="ARG",
+                    help="write profiles/ summaries from rocprofv3 csv output and exit: "
+                         "'trace DIR CMD' (kernel-trace --stats) or "
+                         "'traffic FETCH_DIR WRITE_DIR COPYF_DIR COPYW_DIR CMD' (--pmc passes)")
     return ap.parse_args()
 
 
@@ -85,6 +89,9 @@ def cpu_baseline(lattice, dims, K, S, cells, occ_host, V, seed, beta, budget_s):
 
 def main():
     args = parse()
+    if args.summarize:
+        summarize(args)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus N > 1 is not supported", file=sys.stderr)
         sys.exit(2)
@@ -223,6 +230,84 @@ def kernel_fingerprint() -> str:
         with open(os.path.join(ROOT, "paper_2503_12591_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+# --------------------------------------------------------------------------
+# rocprofv3 csv -> short text summaries under profiles/
+# --------------------------------------------------------------------------
+def _csv(d, suffix):
+    import csv
+    import glob
+    fs = glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)
+    if not fs:
+        raise SystemExit(f"no *{suffix} under {d}")
+    with open(fs[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _per_dispatch(d, counter, match):
+    """Average value of a counter over the dispatches whose kernel name contains
+    `match` (one row per dispatch and counter)."""
+    vals = [float(r["Counter_Value"]) for r in _csv(d, "counter_collection.csv")
+            if r["Counter_Name"] == counter and match(r["Kernel_Name"])]
+    if not vals:
+        raise SystemExit(f"no {counter} rows in {d}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def _copy_factor(d, counter, nbytes=1 << 30):
+    """True bytes per counted byte, from the largest dispatch of the copy probe."""
+    rows = [r for r in _csv(d, "counter_collection.csv") if r["Counter_Name"] == counter]
+    kib = max(float(r["Counter_Value"]) for r in rows)
+    return nbytes / (kib * 1024.0), kib
+
+
+def summarize(args):
+    kind, rest = args.summarize[0], args.summarize[1:]
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    tag = f"ministep_bcc{args.edge}_ell{args.ell}"
+    if kind == "trace":
+        d, cmd = rest[0], " ".join(rest[1:])
+        rows = _csv(d, "kernel_stats.csv")
+        rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+        lines = [f"# rocprofv3 kernel trace: BCC {args.edge}^3 benchmark, link cell {args.ell}",
+                 f"# command: {cmd}", "",
+                 f"{'calls':>7} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_ms':>10} {'pct':>6}  kernel"]
+        for r in rows:
+            name = r["Name"]
+            if len(name) > 110:
+                name = name[:107] + "..."
+            lines.append(f"{int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.1f} "
+                         f"{float(r['MinNs']) / 1e3:10.1f} {float(r['MaxNs']) / 1e3:10.1f} "
+                         f"{float(r['TotalDurationNs']) / 1e6:10.2f} {float(r['Percentage']):6.2f}  {name}")
+        with open(os.path.join(ROOT, "profiles", f"{tag}_kernel_trace.txt"), "w") as f:
+            f.write("\n".join(lines) + "\n")
+    elif kind == "traffic":
+        fd, wd, cfd, cwd, cmd = rest[0], rest[1], rest[2], rest[3], " ".join(rest[4:])
+        is_k = lambda n: "k_ministep" in n
+        fk, nf = _per_dispatch(fd, "FETCH_SIZE", is_k)
+        wk, nw = _per_dispatch(wd, "WRITE_SIZE", is_k)
+        ff, fcopy = _copy_factor(cfd, "FETCH_SIZE")
+        fw, wcopy = _copy_factor(cwd, "WRITE_SIZE")
+        rd = fk * 1024 * ff
+        wr = wk * 1024 * fw
+        lines = [f"# HBM traffic of k_ministep: BCC {args.edge}^3 benchmark, link cell {args.ell}",
+                 f"# command (one pass per counter): {cmd}",
+                 "# calibration: bench.py --copy-probe (torch copy of 1 GiB) under the same counters", "",
+                 f"FETCH_SIZE per dispatch (KiB, avg over {nf}): {fk:.1f}",
+                 f"WRITE_SIZE per dispatch (KiB, avg over {nw}): {wk:.1f}",
+                 f"copy probe FETCH_SIZE (KiB) for 1 GiB read: {fcopy:.1f} -> factor {ff:.4f}",
+                 f"copy probe WRITE_SIZE (KiB) for 1 GiB written: {wcopy:.1f} -> factor {fw:.4f}",
+                 f"scaled read bytes per launch: {rd:.4e}",
+                 f"scaled write bytes per launch: {wr:.4e}",
+                 f"scaled HBM bytes per launch: {rd + wr:.4e}"]
+        with open(os.path.join(ROOT, "profiles", f"{tag}_traffic.txt"), "w") as f:
+            f.write("\n".join(lines) + "\n")
+        with open(os.path.join(ROOT, "profiles", f"traffic_{tag}.json"), "w") as f:
+            json.dump({"bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
+                       "kernel_build": kernel_fingerprint(), "command": cmd}, f, indent=1)
+    else:
+        raise SystemExit(f"unknown summary kind {kind}")
 
 
 if __name__ == "__main__":

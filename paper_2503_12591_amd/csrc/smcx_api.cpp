@@ -222,7 +222,7 @@ int make_plan(const smcx_desc* d, Plan& P)
         for (const Replica& R : P.reps)
             for (int a = 0; a < 3; ++a)
                 for (int e : R.edges[a]) uniform &= e == q.ell;
-        if (!uniform || P.K > 5 || P.nbuf != 1) continue;
+        if (!uniform || P.K != q.K || P.S != q.S || P.nbuf != 1) continue;
         P.preset = pi;
         P.LP = preset_LP(q);
         P.WY = preset_WY(q);

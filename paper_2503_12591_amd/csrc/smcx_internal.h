@@ -156,14 +156,14 @@ struct RepDev {
 // TX*ELL*m divisible by 16 starts at floor16(m*o) past the tile origin.
 // ---------------------------------------------------------------------------
 struct Preset {
-    int lattice, tx, ty, tz, ell;
+    int lattice, tx, ty, tz, ell, K, S;
 };
 
 constexpr Preset kPresets[] = {
-    {SMCX_BCC, 16, 4, 4, 4},
-    {SMCX_BCC, 16, 4, 2, 4},
-    {SMCX_FCC, 16, 4, 2, 4},
-    {SMCX_FCC, 8, 4, 4, 4},
+    {SMCX_BCC, 16, 4, 4, 4, 4, 4},  // 4-component BCC alloy, 4 shells
+    {SMCX_BCC, 16, 4, 2, 4, 4, 4},
+    {SMCX_FCC, 16, 4, 2, 4, 5, 4},  // 5-component FCC alloy, 4 shells
+    {SMCX_FCC, 8, 4, 4, 4, 5, 4},
 };
 constexpr int kNumPresets = sizeof(kPresets) / sizeof(kPresets[0]);
 

@@ -219,6 +219,8 @@ struct GeoRt {
     __device__ static int WY(const SweepArgs& A) { return A.WY; }
     __device__ static int WZ(const SweepArgs& A) { return A.WZ; }
     __device__ static int block(const SweepArgs&) { return blockDim.x; }
+    __device__ static int K(const SweepArgs& A) { return A.K; }
+    __device__ static int S(const SweepArgs& A) { return A.S; }
 };
 
 template <int PI>
@@ -234,6 +236,8 @@ struct GeoFix {
     __device__ static constexpr int WY(const SweepArgs&) { return preset_WY(P); }
     __device__ static constexpr int WZ(const SweepArgs&) { return preset_WZ(P); }
     __device__ static constexpr int block(const SweepArgs&) { return (P.tx * P.ty * P.tz + 63) / 64 * 64; }
+    __device__ static constexpr int K(const SweepArgs&) { return P.K; }
+    __device__ static constexpr int S(const SweepArgs&) { return P.S; }
 };
 
 struct TileGeom {
@@ -377,60 +381,96 @@ struct StagePlan {
     }
 };
 
-// One lane's trial on the staged window `win`.  Returns flags: bit0 active,
-// bit1 accepted, bit2 near-tie.
+// A trial is split at the point where it stops reading the tile window:
+// trial_read draws the random numbers and forms the packed neighbour counts
+// from LDS, trial_finish turns them into dE, takes the Metropolis decision
+// and writes the swap.  Between the two the window buffer may be refilled.
+template <int E>
+struct LaneState {
+    using CT = typename Enc<E>::T;
+    int active = 0;
+    int p8 = 0, q8 = 0, k = 0, b = 0;
+    CT Ca[kMaxShells], Cb[kMaxShells];
+    uint32_t w1 = 0, w2 = 0;
+    int ax = 0, ay = 0, az = 0;
+    int64_t ia = 0;
+};
+
 template <int LAT, int E, int B, class Geo>
-__device__ __forceinline__ int lane_trial(const SweepArgs& A, const RepDev& rep, uint8_t* pad, const Lds& T,
-                                          const uint8_t* win, const TileGeom& tg, int r, uint32_t t, double beta,
-                                          int ax, int ay, int az)
+__device__ __forceinline__ void trial_read(const SweepArgs& A, const RepDev& rep, const Lds& T, const uint8_t* win,
+                                           const TileGeom& tg, int r, uint32_t t, int ax, int ay, int az,
+                                           LaneState<E>& L)
+{
+    using CT = typename Enc<E>::T;
+    constexpr Geometry G = kGeom[LAT];
+    constexpr int m = G.m;
+    constexpr int Z1 = G.Z[0];
+    const int LP = Geo::LP(A), WY = Geo::WY(A), PL = LP * WY;
+    const int S = Geo::S(A);
+    const int la = ((az - tg.w0[2]) * WY + (ay - tg.w0[1])) * LP + (m * (ax + kHalo) + B - tg.gx0);
+    const int64_t ia = B + (int64_t)m * (ax + (int64_t)rep.L[0] * (ay + (int64_t)rep.L[1] * az));
+    uint32_t w0, w1, w2, w3;
+    philox4x32_10((uint32_t)ia, (uint32_t)((uint64_t)ia >> 32), t, (uint32_t)r, (uint32_t)A.seed,
+                  (uint32_t)(A.seed >> 32), w0, w1, w2, w3);
+    (void)w3;
+    const int k = (int)__umulhi(w0, (uint32_t)Z1);
+    const int p8 = win[la];
+    const int offb = T.offB[B * Z1 + k];
+    const int q8 = win[la + offb];
+    L.active = 1;
+    L.p8 = p8;
+    L.q8 = q8;
+    L.k = k;
+    L.b = B;
+    L.w1 = w1;
+    L.w2 = w2;
+    L.ax = ax;
+    L.ay = ay;
+    L.az = az;
+    L.ia = ia;
+    if (p8 == q8) return;
+    count_uniform<LAT, B, CT>(win, la, LP, PL, S, L.Ca);
+    if constexpr (LAT == SMCX_BCC) {
+        // the partner of a BCC site always sits on the other sublattice
+        count_uniform<LAT, 1 - B, CT>(win, la + offb, LP, PL, S, L.Cb);
+    } else {
+        count_table<LAT, CT>(win, la, T.offP + (B * Z1 + k) * A.sumZ, S, L.Cb);
+    }
+}
+
+// Returns flags: bit0 active, bit1 accepted, bit2 near-tie (0 for an idle lane).
+template <int LAT, int E, class Geo>
+__device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& rep, uint8_t* pad, const Lds& T,
+                                            int r, uint32_t t, double beta, const LaneState<E>& L)
 {
     using EN = Enc<E>;
     using CT = typename EN::T;
     constexpr Geometry G = kGeom[LAT];
     constexpr int m = G.m;
-    const int LP = Geo::LP(A), WY = Geo::WY(A), PL = LP * WY;
-    const int la = ((az - tg.w0[2]) * WY + (ay - tg.w0[1])) * LP + (m * (ax + kHalo) + B - tg.gx0);
-    const int64_t ia = B + (int64_t)m * (ax + (int64_t)rep.L[0] * (ay + (int64_t)rep.L[1] * az));
-
-    uint32_t w0, w1, w2, w3;
-    philox4x32_10((uint32_t)ia, (uint32_t)((uint64_t)ia >> 32), t, (uint32_t)r, (uint32_t)A.seed,
-                  (uint32_t)(A.seed >> 32), w0, w1, w2, w3);
-    (void)w3;
-    const int k = (int)__umulhi(w0, (uint32_t)A.Z1);
-    const int p8 = win[la];
-    const int offb = T.offB[B * A.Z1 + k];
-    const int q8 = win[la + offb];
-    if (p8 == q8) return 1;
-
-    CT Ca[kMaxShells], Cb[kMaxShells];
-    count_uniform<LAT, B, CT>(win, la, LP, PL, A.S, Ca);
-    if constexpr (LAT == SMCX_BCC) {
-        // the partner of a BCC site always sits on the other sublattice
-        count_uniform<LAT, 1 - B, CT>(win, la + offb, LP, PL, A.S, Cb);
-    } else {
-        count_table<LAT, CT>(win, la, T.offP + (B * A.Z1 + k) * A.sumZ, A.S, Cb);
-    }
-
+    constexpr int Z1 = G.Z[0];
+    if (!L.active) return 0;
+    if (L.p8 == L.q8) return 1;
+    const int K = Geo::K(A), S = Geo::S(A);
+    const int p8 = L.p8, q8 = L.q8, k = L.k;
     // species were checked < K at init; the clamp keeps table reads in bounds regardless
-    const int p = min(species_of(p8, EN::F), A.K - 1), q = min(species_of(q8, EN::F), A.K - 1);
-    const double* Dp = T.D + (size_t)((p * A.K + q) * A.S) * A.K;
+    const int p = min(species_of(p8, EN::F), K - 1), q = min(species_of(q8, EN::F), K - 1);
+    const double* Dp = T.D + (size_t)((p * K + q) * S) * K;
     double dE = 0.0;
 #pragma unroll
     for (int s = 0; s < kMaxShells; ++s) {
-        if (s < A.S) {
+        if (s < S) {
             // images of the partner inside shell s (1, 0, 0, 0 unless an edge is 2)
             const CT mu = rep.alias ? (CT)rep.mult[s][k] : (CT)(s == 0 ? 1 : 0);
-            const CT d = Ca[s] + EN::bias - Cb[s] + (mu << p8) - (mu << q8);
+            const CT d = L.Ca[s] + EN::bias - L.Cb[s] + (mu << p8) - (mu << q8);
 #pragma unroll
             for (int tt = 0; tt < EN::KP; ++tt) {
-                if (tt < A.K) {
+                if (tt < K) {
                     const int c = (int)((d >> (EN::F * tt)) & EN::mask) - EN::half;
-                    dE = dE + (double)c * Dp[s * A.K + tt];
+                    dE = dE + (double)c * Dp[s * K + tt];
                 }
             }
         }
     }
-
     bool acc;
     bool tie = false;
     if (dE <= 0.0) {
@@ -438,7 +478,7 @@ __device__ __forceinline__ int lane_trial(const SweepArgs& A, const RepDev& rep,
     } else {
         const double x = beta * dE;
         const double P = exp(-x);
-        const double u = (double)(((uint64_t)w1 << 21) | (uint64_t)(w2 >> 11)) * 0x1p-53;
+        const double u = (double)(((uint64_t)L.w1 << 21) | (uint64_t)(L.w2 >> 11)) * 0x1p-53;
         acc = u < P;
         tie = fabs(u - P) < 1e-12;
     }
@@ -448,40 +488,40 @@ __device__ __forceinline__ int lane_trial(const SweepArgs& A, const RepDev& rep,
             smcx_tie e;
             e.replica = r;
             e.sweep = t;
-            e.site = ia;
+            e.site = L.ia;
             e.decision = acc ? 1 : 0;
             e.pad = 0;
             A.ties[slot] = e;
         }
     }
     if (acc) {
-        const int8_t* pd = T.pd + (B * A.Z1 + k) * 4;
-        int bx = ax + pd[0], by = ay + pd[1], bz = az + pd[2];
+        const int8_t* pd = T.pd + (L.b * Z1 + k) * 4;
+        int bx = L.ax + pd[0], by = L.ay + pd[1], bz = L.az + pd[2];
         const int bb = pd[3];
         bx += bx < 0 ? rep.L[0] : (bx >= rep.L[0] ? -rep.L[0] : 0);
         by += by < 0 ? rep.L[1] : (by >= rep.L[1] ? -rep.L[1] : 0);
         bz += bz < 0 ? rep.L[2] : (bz >= rep.L[2] ? -rep.L[2] : 0);
         // the padded copy holds F * species, like the window
-        store_site(pad, rep, m, ax, ay, az, B, (uint8_t)q8);
+        store_site(pad, rep, m, L.ax, L.ay, L.az, L.b, (uint8_t)q8);
         store_site(pad, rep, m, bx, by, bz, bb, (uint8_t)p8);
     }
     return 1 | (acc ? 2 : 0) | (tie ? 4 : 0);
 }
 
 template <int LAT, int E, class Geo>
-__device__ __forceinline__ int lane_dispatch(int b, const SweepArgs& A, const RepDev& rep, uint8_t* pad,
-                                             const Lds& T, const uint8_t* win, const TileGeom& tg, int r,
-                                             uint32_t t, double beta, int ax, int ay, int az)
+__device__ __forceinline__ void read_dispatch(int b, const SweepArgs& A, const RepDev& rep, const Lds& T,
+                                              const uint8_t* win, const TileGeom& tg, int r, uint32_t t, int ax,
+                                              int ay, int az, LaneState<E>& L)
 {
     if constexpr (LAT == SMCX_BCC) {
-        if (b == 0) return lane_trial<LAT, E, 0, Geo>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
-        return lane_trial<LAT, E, 1, Geo>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
+        if (b == 0) trial_read<LAT, E, 0, Geo>(A, rep, T, win, tg, r, t, ax, ay, az, L);
+        else trial_read<LAT, E, 1, Geo>(A, rep, T, win, tg, r, t, ax, ay, az, L);
     } else {
         switch (b) {
-        case 0: return lane_trial<LAT, E, 0, Geo>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
-        case 1: return lane_trial<LAT, E, 1, Geo>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
-        case 2: return lane_trial<LAT, E, 2, Geo>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
-        default: return lane_trial<LAT, E, 3, Geo>(A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
+        case 0: trial_read<LAT, E, 0, Geo>(A, rep, T, win, tg, r, t, ax, ay, az, L); break;
+        case 1: trial_read<LAT, E, 1, Geo>(A, rep, T, win, tg, r, t, ax, ay, az, L); break;
+        case 2: trial_read<LAT, E, 2, Geo>(A, rep, T, win, tg, r, t, ax, ay, az, L); break;
+        default: trial_read<LAT, E, 3, Geo>(A, rep, T, win, tg, r, t, ax, ay, az, L); break;
         }
     }
 }
@@ -520,12 +560,14 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Trials of the lanes of one staged tile (one lane per link cell).
+// First half of the trials of one staged tile (one lane per link cell):
+// lanes outside the tile or whose cell is shorter than an offset stay idle.
 template <int LAT, int E, class Geo>
-__device__ __forceinline__ void tile_trials(const SweepArgs& A, const RepDev& rep, int r, const TileGeom& tg,
-                                            int b, const int (&o)[3], uint32_t t, double beta, const Lds& T,
-                                            const uint8_t* win, Stats& st)
+__device__ __forceinline__ void tile_read(const SweepArgs& A, const RepDev& rep, int r, const TileGeom& tg, int b,
+                                          const int (&o)[3], uint32_t t, const Lds& T, const uint8_t* win,
+                                          LaneState<E>& L)
 {
+    L.active = 0;
     const int l = threadIdx.x;
     const int lx = l % Geo::T(A, 0);
     const int ly = (l / Geo::T(A, 0)) % Geo::T(A, 1);
@@ -540,11 +582,27 @@ __device__ __forceinline__ void tile_trials(const SweepArgs& A, const RepDev& re
               az < cell_origin<Geo>(A, rep, 2, cz + 1)))
             return;
     }
-    uint8_t* pad = A.ws + rep.pad_off;
-    const int f = lane_dispatch<LAT, E, Geo>(b, A, rep, pad, T, win, tg, r, t, beta, ax, ay, az);
-    st.att += 1;
+    read_dispatch<LAT, E, Geo>(b, A, rep, T, win, tg, r, t, ax, ay, az, L);
+}
+
+template <int LAT, int E, class Geo>
+__device__ __forceinline__ void tile_finish(const SweepArgs& A, const RepDev& rep, int r, uint32_t t, double beta,
+                                            const Lds& T, const LaneState<E>& L, Stats& st)
+{
+    const int f = trial_finish<LAT, E, Geo>(A, rep, A.ws + rep.pad_off, T, r, t, beta, L);
+    st.att += f & 1;
     st.acc += (f >> 1) & 1;
     st.tie += (f >> 2) & 1;
+}
+
+template <int LAT, int E, class Geo>
+__device__ __forceinline__ void tile_trials(const SweepArgs& A, const RepDev& rep, int r, const TileGeom& tg,
+                                            int b, const int (&o)[3], uint32_t t, double beta, const Lds& T,
+                                            const uint8_t* win, Stats& st)
+{
+    LaneState<E> L;
+    tile_read<LAT, E, Geo>(A, rep, r, tg, b, o, t, T, win, L);
+    tile_finish<LAT, E, Geo>(A, rep, r, t, beta, T, L, st);
 }
 
 // Tiles first, first + step, ... (< end) of a logical tile space for mini-step
