@@ -160,7 +160,8 @@ def main():
     secs = ms / 1e3
     value = attempted / secs
     avg_launch_s = kern_ms / 1e3 / max(launches, 1)
-    bytes_per_launch = algorithmic_bytes_per_launch(cells, N, 2)
+    launches_per_sweep = launches / (args.steps * spst)
+    bytes_per_launch = algorithmic_bytes_per_launch(cells, N, 2, launches_per_sweep)
     achieved = bytes_per_launch / avg_launch_s / 1e9 if args.mode == "stream" else None
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_ministep_bcc{args.edge}_ell{args.ell}.json")
@@ -204,21 +205,23 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def algorithmic_bytes_per_launch(cells, N, m):
-    """Average algorithmic HBM bytes of one mini-step launch.  A mini-step with
-    offsets o reads every occupancy byte of the link cells that have o (the
-    LIZ+ regions of their active sites cover those cells) and writes at most 2
-    bytes per trial; with uniform cells that is N + 2 n_C."""
+def algorithmic_bytes_per_launch(cells, N, m, launches_per_sweep):
+    """Average algorithmic HBM bytes of one sweep launch.  The mini-steps of
+    one offset o read every occupancy byte of the link cells that have o (the
+    LIZ+ regions of their active sites cover those cells) -- once per launch,
+    since a launch covers consecutive basis sites of one o -- and every trial
+    writes at most 2 bytes (2N per sweep).  With uniform cells and all m basis
+    sites in one launch that is N + 2 m n_C."""
     M = [int(max(c)) for c in cells]
-    total = 0.0
+    n_o = M[0] * M[1] * M[2]
+    reads = 0.0
     for oz in range(M[2]):
         for oy in range(M[1]):
             for ox in range(M[0]):
                 act = [(np.asarray(cells[a]) > o).sum() for a, o in enumerate((ox, oy, oz))]
-                frac = np.prod([act[a] / len(cells[a]) for a in range(3)])
-                n_act = int(np.prod(act))
-                total += m * (frac * N + 2 * n_act)
-    return total / (m * M[0] * M[1] * M[2])
+                reads += np.prod([act[a] / len(cells[a]) for a in range(3)]) * N
+    per_sweep = reads * (launches_per_sweep / n_o) + 2 * N
+    return per_sweep / launches_per_sweep
 
 
 def kernel_fingerprint() -> str:

@@ -107,7 +107,7 @@ typedef struct {
                               least the minimum unless the axis has one cell */
     int32_t tile[3];       /* link cells per workgroup tile along x, y, z
                               (product <= 256), or {0,0,0} for the default
-                              (16,4,4) on BCC, (16,4,2) on FCC */
+                              (16,4,2) */
     uint32_t flags;        /* SMCX_FLAG_* bits */
 } smcx_desc;
 

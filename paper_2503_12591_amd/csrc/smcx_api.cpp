@@ -47,6 +47,20 @@ int min_edge(int lattice, int S)
     return ell;
 }
 
+// Smallest cell edge for which the trials of consecutive basis sites at one
+// offset may share a staged window: a lane's next site moves by up to one
+// half-lattice unit per axis, so other cells' written sites (within one unit
+// of their active sites) must stay beyond the read reach 1 + c_max of it:
+// 2 * ell - 1 > 2 + c_max.  The same bound keeps periodic images of a
+// written site out of that reach.
+int group_edge(int lattice, int S)
+{
+    const int c = max_component(kGeom[lattice], S);
+    int ell = 1;
+    while (!(2 * ell > 3 + c)) ++ell;
+    return ell;
+}
+
 struct Replica {
     int L[3];
     std::vector<int> edges[3];
@@ -67,6 +81,7 @@ struct Plan {
     int T[3];
     int block;  // threads per workgroup: the tile's link cells rounded up to whole waves
     int nbuf;   // window buffers per workgroup
+    int group;  // mini-steps of consecutive basis sites sharing one staged window (m, or 1 if an edge < 4)
     int preset; // compile-time window preset of the stream kernel, or -1
     std::vector<Replica> reps;
     int LP, WY, WZ;
@@ -93,12 +108,14 @@ int make_plan(const smcx_desc* d, Plan& P)
     P.S = d->n_shells;
     P.R = d->n_replicas;
     P.m = lattice_m(P.lattice);
+    P.group = P.m;
+    const int gedge = group_edge(P.lattice, d->n_shells);
     const Geometry& G = kGeom[P.lattice];
     P.Z1 = G.Z[0];
     P.sumZ = sum_Z(G, P.S);
     const int emin = min_edge(P.lattice, P.S);
     if (d->tile[0] == 0 && d->tile[1] == 0 && d->tile[2] == 0) {
-        P.T[0] = 16; P.T[1] = 4; P.T[2] = P.lattice == SMCX_BCC ? 4 : 2;
+        P.T[0] = 16; P.T[1] = 4; P.T[2] = 2;
     } else {
         for (int a = 0; a < 3; ++a) {
             if (d->tile[a] < 1) return fail(SMCX_E_INVALID_ARG, "tile edges must be >= 1");
@@ -160,6 +177,7 @@ int make_plan(const smcx_desc* d, Plan& P)
             for (int e : R.edges[a]) {
                 R.origin[a].push_back(R.origin[a].back() + e);
                 R.M[a] = std::max(R.M[a], e);
+                if (e < gedge) P.group = 1;
             }
             R.ntile[a] = ((int)R.edges[a].size() + P.T[a] - 1) / P.T[a];
         }
@@ -318,6 +336,7 @@ SweepArgs base_args(smcx_lattice* h)
     a.win_bytes = P.lds.win_bytes;
     a.nbuf = P.nbuf;
     a.only_rep = -1;
+    a.nb = 1;
     a.sweep_counter = nullptr;
     return a;
 }
@@ -586,18 +605,23 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
     a.n_sweeps = n_sweeps;
     a.tau_begin = tau_begin;
     a.tau_end = tau_end;
+    // one launch per group of mini-steps that share an offset (and a window)
+    auto group_end = [&](int g, int end) { return std::min(end, (g / P.group + 1) * P.group); };
     if (mode == SMCX_MODE_PERSISTENT) {
         a.first_sweep = first_sweep;
         a.beta = beta_dev;
         a.beta_stride = P.R;
+        a.nb = P.group;
         if (int rc = timed_launch(h, true, dim3(P.R), st, a)) return rc;
     } else if (mode == SMCX_MODE_STREAM) {
         const dim3 grid((unsigned)std::min<int64_t>(h->stream_wgs, 8 * ((P.total_tiles + 7) / 8)));
         for (int js = 0; js < n_sweeps; ++js) {
             a.first_sweep = first_sweep + (uint32_t)js;
             a.beta = beta_dev + (int64_t)js * P.R;
-            for (int g = tau_begin; g < std::min(tau_end, P.max_nA); ++g) {
+            const int end = std::min(tau_end, P.max_nA);
+            for (int g = tau_begin; g < end; g = group_end(g, end)) {
                 a.g = g;
+                a.nb = group_end(g, end) - g;
                 if (int rc = timed_launch(h, false, grid, st, a)) return rc;
             }
         }
@@ -608,8 +632,10 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
             for (int r = 0; r < P.R; ++r) {
                 a.only_rep = r;
                 const dim3 grid((unsigned)std::min<int64_t>(h->stream_wgs, 8 * ((P.reps[r].ntiles + 7) / 8)));
-                for (int g = tau_begin; g < std::min(tau_end, P.reps[r].nA); ++g) {
+                const int end = std::min(tau_end, P.reps[r].nA);
+                for (int g = tau_begin; g < end; g = group_end(g, end)) {
                     a.g = g;
+                    a.nb = group_end(g, end) - g;
                     if (int rc = timed_launch(h, false, grid, st, a)) return rc;
                 }
             }
@@ -779,6 +805,7 @@ int smcx_ladder_capture(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, const 
     a.beta_stride = 0;
     a.tau_begin = 0;
     a.tau_end = P.max_nA;
+    a.nb = P.group;
     int rc = pack_all(h, false, st);
     hipError_t e = hipSuccess;
     if (rc == SMCX_OK) e = launch_sweep(h->k_persistent, dim3(P.R), P.block, P.lds.total, st, a);

@@ -393,6 +393,7 @@ struct LaneState {
     CT Ca[kMaxShells], Cb[kMaxShells];
     uint32_t w1 = 0, w2 = 0;
     int ax = 0, ay = 0, az = 0;
+    int la = 0, lb = 0;  // window bytes of the two sites
     int64_t ia = 0;
 };
 
@@ -428,6 +429,8 @@ __device__ __forceinline__ void trial_read(const SweepArgs& A, const RepDev& rep
     L.ay = ay;
     L.az = az;
     L.ia = ia;
+    L.la = la;
+    L.lb = la + offb;
     if (p8 == q8) return;
     count_uniform<LAT, B, CT>(win, la, LP, PL, S, L.Ca);
     if constexpr (LAT == SMCX_BCC) {
@@ -441,7 +444,7 @@ __device__ __forceinline__ void trial_read(const SweepArgs& A, const RepDev& rep
 // Returns flags: bit0 active, bit1 accepted, bit2 near-tie (0 for an idle lane).
 template <int LAT, int E, class Geo>
 __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& rep, uint8_t* pad, const Lds& T,
-                                            int r, uint32_t t, double beta, const LaneState<E>& L)
+                                            uint8_t* win, int r, uint32_t t, double beta, const LaneState<E>& L)
 {
     using EN = Enc<E>;
     using CT = typename EN::T;
@@ -501,9 +504,12 @@ __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& re
         bx += bx < 0 ? rep.L[0] : (bx >= rep.L[0] ? -rep.L[0] : 0);
         by += by < 0 ? rep.L[1] : (by >= rep.L[1] ? -rep.L[1] : 0);
         bz += bz < 0 ? rep.L[2] : (bz >= rep.L[2] ? -rep.L[2] : 0);
-        // the padded copy holds F * species, like the window
+        // the padded copy holds F * species, like the window; the window copy
+        // serves the next basis site's trial of this lane
         store_site(pad, rep, m, L.ax, L.ay, L.az, L.b, (uint8_t)q8);
         store_site(pad, rep, m, bx, by, bz, bb, (uint8_t)p8);
+        win[L.la] = (uint8_t)q8;
+        win[L.lb] = (uint8_t)p8;
     }
     return 1 | (acc ? 2 : 0) | (tie ? 4 : 0);
 }
@@ -587,22 +593,58 @@ __device__ __forceinline__ void tile_read(const SweepArgs& A, const RepDev& rep,
 
 template <int LAT, int E, class Geo>
 __device__ __forceinline__ void tile_finish(const SweepArgs& A, const RepDev& rep, int r, uint32_t t, double beta,
-                                            const Lds& T, const LaneState<E>& L, Stats& st)
+                                            const Lds& T, uint8_t* win, const LaneState<E>& L, Stats& st)
 {
-    const int f = trial_finish<LAT, E, Geo>(A, rep, A.ws + rep.pad_off, T, r, t, beta, L);
+    const int f = trial_finish<LAT, E, Geo>(A, rep, A.ws + rep.pad_off, T, win, r, t, beta, L);
     st.att += f & 1;
     st.acc += (f >> 1) & 1;
     st.tie += (f >> 2) & 1;
 }
 
+// Trials of basis sites b0 .. b0 + nb - 1 at the same offsets o, each lane in
+// its own link cell.  One window serves them all: a lane's trial at b + 1
+// reads within two conventional cells of its site, which no other cell's
+// trial at b writes (the sites of two cells stay at least three cells apart
+// on some axis), so the lane's own accepted swap, written back into the
+// window, is the only change it can see.  (Needs every edge >= 4, so that no
+// periodic image of a written site lies in that reach.)
 template <int LAT, int E, class Geo>
 __device__ __forceinline__ void tile_trials(const SweepArgs& A, const RepDev& rep, int r, const TileGeom& tg,
-                                            int b, const int (&o)[3], uint32_t t, double beta, const Lds& T,
-                                            const uint8_t* win, Stats& st)
+                                            int b0, int nb, const int (&o)[3], uint32_t t, double beta,
+                                            const Lds& T, uint8_t* win, Stats& st)
 {
-    LaneState<E> L;
-    tile_read<LAT, E, Geo>(A, rep, r, tg, b, o, t, T, win, L);
-    tile_finish<LAT, E, Geo>(A, rep, r, t, beta, T, L, st);
+    for (int j = 0; j < nb; ++j) {
+        LaneState<E> L;
+        tile_read<LAT, E, Geo>(A, rep, r, tg, b0 + j, o, t, T, win, L);
+        tile_finish<LAT, E, Geo>(A, rep, r, t, beta, T, win, L, st);
+    }
+}
+
+// The replica table is read-only during a launch: reading it through the
+// constant address space (with a wave-uniform index) lets the compiler use
+// scalar loads instead of per-lane ones.
+__device__ __forceinline__ const RepDev& rep_of(const SweepArgs& A, int r)
+{
+    using CRep = const __attribute__((address_space(4))) RepDev;
+    return *(const RepDev*)((CRep*)A.reps + r);
+}
+
+// Same for other tables a launch only reads (tile prefix sums, betas).
+template <typename T>
+__device__ __forceinline__ T ld_const(const T* p, int64_t i)
+{
+    using CT = const __attribute__((address_space(4))) T;
+    return ((CT*)p)[i];
+}
+
+// The replica and tile of a loop step are the same in every lane; saying so
+// lets the compiler read the replica's table through scalar loads.
+__device__ __forceinline__ void uniform(int& r, int64_t& tile)
+{
+    r = __builtin_amdgcn_readfirstlane(r);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)tile);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)tile >> 32));
+    tile = (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // Tiles first, first + step, ... (< end) of a logical tile space for mini-step
@@ -613,7 +655,7 @@ __device__ __forceinline__ void tile_trials(const SweepArgs& A, const RepDev& re
 // beta_of(r) gives the replica's inverse temperature.  Every thread calls this
 // with the same arguments.
 template <int LAT, int E, class Geo, int NBUF, typename TileOf, typename BetaOf>
-__device__ void run_tiles(const SweepArgs& A, int64_t first, int64_t end, int64_t step, int tau, uint32_t t,
+__device__ void run_tiles(const SweepArgs& A, int64_t first, int64_t end, int64_t step, int tau, int nb, uint32_t t,
                           const Lds& T, uint8_t* win0, uint8_t* win1, TileOf tile_of, BetaOf beta_of, Stats& st,
                           int& r_stats)
 {
@@ -633,7 +675,8 @@ __device__ void run_tiles(const SweepArgs& A, int64_t first, int64_t end, int64_
             int r;
             int64_t tile;
             tile_of(i, r, tile);
-            const RepDev& rep = A.reps[r];
+            uniform(r, tile);
+            const RepDev& rep = rep_of(A, r);
             if (tau >= rep.nA) continue;  // uniform across the block
             int o[3], b;
             offsets(rep, o, b);
@@ -662,19 +705,20 @@ __device__ void run_tiles(const SweepArgs& A, int64_t first, int64_t end, int64_
                 flush_stats(A, r_stats, st);
                 r_stats = r;
             }
-            tile_trials<LAT, E, Geo>(A, rep, r, tg, b, o, t, beta_of(r), T, win0, st);
+            tile_trials<LAT, E, Geo>(A, rep, r, tg, b, nb, o, t, beta_of(r), T, win0, st);
         }
         return;
     }
     int r = 0, rn = 0;
     int64_t tile = 0, tilen = 0;
     tile_of(first, r, tile);
+    uniform(r, tile);
     int o[3], b;
     TileGeom tg;
     bool have;
     constexpr bool dbl = true;
     {
-        const RepDev& rep = A.reps[r];
+        const RepDev& rep = rep_of(A, r);
         offsets(rep, o, b);
         have = tau < rep.nA && tile_geometry<LAT, Geo>(A, rep, tile, o, tg);
         if (have && dbl) stage_async<LAT, Geo>(A, rep, tg, A.ws + rep.pad_off, win0);
@@ -687,7 +731,8 @@ __device__ void run_tiles(const SweepArgs& A, int64_t first, int64_t end, int64_
         bool haven = false;
         if (inext < end) {
             tile_of(inext, rn, tilen);
-            const RepDev& repn = A.reps[rn];
+            uniform(rn, tilen);
+            const RepDev& repn = rep_of(A, rn);
             offsets(repn, on, bn);
             haven = tau < repn.nA && tile_geometry<LAT, Geo>(A, repn, tilen, on, tgn);
         }
@@ -696,9 +741,9 @@ __device__ void run_tiles(const SweepArgs& A, int64_t first, int64_t end, int64_
         uint8_t* cur = win0;
         if (dbl) {
             cur = (k & 1) ? win1 : win0;
-            if (haven) stage_async<LAT, Geo>(A, A.reps[rn], tgn, A.ws + A.reps[rn].pad_off, (k & 1) ? win0 : win1);
+            if (haven) stage_async<LAT, Geo>(A, rep_of(A, rn), tgn, A.ws + rep_of(A, rn).pad_off, (k & 1) ? win0 : win1);
         } else if (have) {
-            stage_async<LAT, Geo>(A, A.reps[r], tg, A.ws + A.reps[r].pad_off, win0);
+            stage_async<LAT, Geo>(A, rep_of(A, r), tg, A.ws + rep_of(A, r).pad_off, win0);
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
         }
@@ -707,7 +752,7 @@ __device__ void run_tiles(const SweepArgs& A, int64_t first, int64_t end, int64_
                 flush_stats(A, r_stats, st);
                 r_stats = r;
             }
-            tile_trials<LAT, E, Geo>(A, A.reps[r], r, tg, b, o, t, beta_of(r), T, cur, st);
+            tile_trials<LAT, E, Geo>(A, rep_of(A, r), r, tg, b, nb, o, t, beta_of(r), T, cur, st);
         }
         r = rn;
         tile = tilen;
@@ -748,15 +793,15 @@ __global__ __launch_bounds__(kBlock) void k_ministep(SweepArgs A)
         int a = 0, z = A.R - 1;  // last replica with tile_off[r] <= i
         while (a < z) {
             const int mid = (a + z + 1) >> 1;
-            if (A.tile_off[mid] <= i) a = mid; else z = mid - 1;
+            if (ld_const(A.tile_off, mid) <= i) a = mid; else z = mid - 1;
         }
         r = a;
-        tile = i - A.tile_off[a];
+        tile = i - ld_const(A.tile_off, a);
     };
-    auto beta_of = [&](int r) { return A.beta[r]; };
+    auto beta_of = [&](int r) { return ld_const(A.beta, r); };
     Stats st;
     int r_stats = -1;
-    run_tiles<LAT, E, Geo, NBUF>(A, lo + blockIdx.x / 8, hi, W, A.g, A.first_sweep, T, smem + A.lds_win,
+    run_tiles<LAT, E, Geo, NBUF>(A, lo + blockIdx.x / 8, hi, W, A.g, A.nb, A.first_sweep, T, smem + A.lds_win,
                            smem + A.lds_win + A.win_bytes, tile_of, beta_of, st, r_stats);
     flush_stats(A, r_stats, st);
 }
@@ -771,7 +816,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(SweepArgs A)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     const int r = blockIdx.x;
-    const RepDev& rep = A.reps[r];
+    const RepDev& rep = rep_of(A, r);
     load_tables<LAT>(A, smem);
     const Lds T = lds_ptrs(A, smem);
     const uint32_t first = A.sweep_counter ? *A.sweep_counter : A.first_sweep;
@@ -784,13 +829,16 @@ __global__ __launch_bounds__(kBlock) void k_persistent(SweepArgs A)
     const int tau_end = min(A.tau_end, rep.nA);
     for (int js = 0; js < A.n_sweeps; ++js) {
         const uint32_t t = first + (uint32_t)js;
-        const double beta = A.beta[(int64_t)js * A.beta_stride + r];
+        const double beta = ld_const(A.beta, (int64_t)js * A.beta_stride + r);
         auto beta_of = [&](int) { return beta; };
-        for (int tau = A.tau_begin; tau < tau_end; ++tau) {
+        for (int tau = A.tau_begin; tau < tau_end;) {
+            // mini-steps of consecutive basis sites at one offset share a window
+            const int nb = min(A.nb - tau % A.nb, tau_end - tau);
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();  // the previous mini-step's writes are visible to every wave
-            run_tiles<LAT, E, Geo, 1>(A, 0, rep.ntiles, 1, tau, t, T, smem + A.lds_win,
+            run_tiles<LAT, E, Geo, 1>(A, 0, rep.ntiles, 1, tau, nb, t, T, smem + A.lds_win,
                                    smem + A.lds_win + A.win_bytes, tile_of, beta_of, st, r_stats);
+            tau += nb;
         }
     }
     flush_stats(A, r_stats, st);
