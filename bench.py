@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ladder", action="store_true",
+                    help="skip the batched-ladder vs plain-loop comparison")
+    ap.add_argument("--ladder-sweeps", type=int, default=20)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--summarize", nargs="+", metavar="ARG",
@@ -197,12 +200,75 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "wall_s": wall,
     }
+    if not args.no_ladder:
+        print("[bench] ladder", file=sys.stderr, flush=True)
+        out["ladder"] = ladder_bench(args)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(lattice, dims, K, S, cells, occ_host, V, seed, beta,
                                            args.cpu_seconds)
     lat.close()
     print(json.dumps(out), flush=True)
+
+
+def ladder_bench(args):
+    """Temperature ladder of 256 cubic BCC replicas with edges drawn from
+    16..48 (4 species, 4 shells, T_r = 300 * 10^(r/255) K): attempted swaps/s
+    of the batched launches (stream: one launch per mini-step group over all
+    replicas; persistent: one launch for all sweeps; graph: that launch
+    captured once and replayed; tuned: the autotuner's pick) against the plain
+    loop that launches every replica's mini-steps one replica at a time."""
+    import torch
+    from paper_2503_12591_amd import inputs as I
+    from paper_2503_12591_amd import smcx
+    lad = I.c4a_ladder()
+    occ = np.concatenate([lad.occ(r) for r in range(lad.R)])
+    N = int(occ.size)
+    dims = lad.dims()
+    occ_dev = torch.from_numpy(occ).cuda()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    res = {}
+    n = args.ladder_sweeps
+    work = occ_dev.clone()
+    lat = smcx.Lattice(I.BCC, dims, lad.K, lad.S, work, ell=4)
+    lat.set_epi(lad.V)
+    sweep_no = 0
+    for mode, ns in (("plain", 2), ("stream", n), ("persistent", n)):
+        bt = np.tile(lad.betas, (ns, 1))
+        lat.sweep(1, 0, lad.betas.reshape(1, -1), first_sweep=sweep_no, mode=mode)  # warm-up
+        sweep_no += 1
+        secs = timed(lambda: lat.sweep(ns, 0, bt, first_sweep=sweep_no, mode=mode))
+        sweep_no += ns
+        res[mode] = ns * N / secs
+    g = smcx.LadderGraph(lat, n, 0, lad.betas, first_sweep=sweep_no)
+    g.launch()  # warm-up replay
+    secs = timed(g.launch)
+    res["graph"] = n * N / secs
+    g.close()
+    lat.close()
+    best = smcx.autotune(I.BCC, dims, lad.K, lad.S, occ_dev, lad.V, lad.betas, sweeps=2)
+    work = occ_dev.clone()
+    lat = smcx.Lattice(I.BCC, dims, lad.K, lad.S, work, ell=best["ell"], tile=best["tile"])
+    lat.set_epi(lad.V)
+    bt = np.tile(lad.betas, (n, 1))
+    lat.sweep(1, 0, lad.betas.reshape(1, -1), mode=best["mode"])
+    secs = timed(lambda: lat.sweep(n, 0, bt, first_sweep=1, mode=best["mode"]))
+    res["tuned"] = n * N / secs
+    lat.close()
+    batched = max(res["stream"], res["persistent"], res["graph"], res["tuned"])
+    return {"workload": "bcc_ladder256_L16to48_k4_s4", "sites": N, "sweeps": n,
+            "unit": "attempted swaps/s", "swaps_per_s": res,
+            "tuned_config": {"tile": best["tile"], "mode": best["mode"], "ell": best["ell"]},
+            "batched_over_plain": batched / res["plain"]}
 
 
 def algorithmic_bytes_per_launch(cells, N, m, launches_per_sweep):

@@ -366,3 +366,132 @@ def EnergyFn():
     if _energy_fn is None:
         _energy_fn = _make_energy_fn()
     return _energy_fn
+
+
+def autotune(lattice: int, dims, K: int, S: int, occ, V, betas, seed: int = 0, tiles=None,
+             modes=("persistent", "stream"), ells=(None,), sweeps: int = 2, cache: str | None = None):
+    """Choose the launch configuration with the most attempted swaps/s.
+
+    Every candidate (tile, mode, link-cell edge) runs `sweeps` sweeps (after
+    one untimed sweep) on a fresh copy of `occ` (host uint8 array or CUDA
+    tensor, all replicas back to back) with inverse temperatures `betas` ([R]
+    or scalar).  Tile and mode leave the trajectory unchanged; a link-cell
+    edge other than None is a different partition, which `Lattice.schedule`
+    exports for replay.  With `cache` (a JSON file), a result for the same
+    geometry and candidate set is reused.  Returns a dict with the best
+    "tile", "mode", "ell", its "swaps_per_s" and the full "table".
+    """
+    import hashlib
+    import json
+    torch = _torch()
+    dims = np.asarray(dims, np.int32).reshape(-1, 3)
+    if tiles is None:
+        tiles = [(16, 4, 2), (16, 4, 4), (8, 4, 4), (8, 8, 2), (4, 4, 4)]
+    key_src = json.dumps([lattice, dims.tolist(), K, S, [list(t) for t in tiles], list(modes),
+                          [e if e is None else int(e) for e in ells], sweeps])
+    key = hashlib.sha256(key_src.encode()).hexdigest()[:16]
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            db = json.load(f)
+        if key in db:
+            return db[key]
+    if isinstance(occ, torch.Tensor):
+        occ0 = occ.detach().to("cuda").contiguous()
+    else:
+        occ0 = torch.from_numpy(np.ascontiguousarray(occ, dtype=np.uint8)).cuda()
+    R = dims.shape[0]
+    N = int((dims.prod(axis=1) * (2 if lattice == BCC else 4)).sum())
+    b1 = np.broadcast_to(np.asarray(betas, np.float64).reshape(-1), (R,))
+    table = []
+    for ell in ells:
+        for tile in tiles:
+            for mode in modes:
+                work = occ0.clone()
+                try:
+                    lat = Lattice(lattice, dims, K, S, work, ell=ell, tile=tile)
+                except SmcxError as e:
+                    table.append({"tile": list(tile), "mode": mode, "ell": ell, "error": str(e)})
+                    continue
+                lat.set_epi(V)
+                bt = np.tile(b1, (sweeps, 1))
+                lat.sweep(1, seed, b1.reshape(1, R), first_sweep=0, mode=mode)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                lat.sweep(sweeps, seed, bt, first_sweep=1, mode=mode)
+                e1.record()
+                torch.cuda.synchronize()
+                secs = e0.elapsed_time(e1) / 1e3
+                table.append({"tile": list(tile), "mode": mode, "ell": ell,
+                              "swaps_per_s": sweeps * N / secs})
+                lat.close()
+                del work
+    ok = [t for t in table if "swaps_per_s" in t]
+    if not ok:
+        raise SmcxError("no candidate configuration could be built")
+    best = dict(max(ok, key=lambda t: t["swaps_per_s"]))
+    best["table"] = table
+    if cache:
+        db = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                db = json.load(f)
+        db[key] = best
+        with open(cache, "w") as f:
+            json.dump(db, f, indent=1)
+    return best
+
+
+def fit_epi(lattice: int, dims, K: int, S: int, occ_batch, e_per_site, steps: int = 1500,
+            lr: float = 1e-2, gamma: float = 0.99):
+    """Fit an EPI to per-site energies of B configurations by Adam, the
+    gradient flowing back through `EnergyFn` (Methods, "The EPI and qSRO
+    model": the EPI is trained with Adam and back-propagation).
+
+    At fixed composition E = const + sum_s sum_{k<l} C_s[k][l] W_s[k][l] with
+    the gauge-invariant W_s[k][l] = V_s[k][l] - (V_s[k][k] + V_s[l][l]) / 2, so
+    only W is identifiable: V is returned in the gauge V_s[k][k] = 0 and the
+    loss compares energies after removing their means.  W is parametrised
+    through the inverse Cholesky factor of the centred feature covariance
+    (features C_s[k][l] / N, k < l), which makes the quadratic loss well
+    conditioned.
+
+    occ_batch: uint8 CUDA tensor [B][N]; e_per_site: [B] float64 (host or
+    CUDA).  Returns (V [S][K][K] float64 CUDA tensor, final relative loss).
+    """
+    torch = _torch()
+    occ_batch = occ_batch.contiguous()
+    B, N = occ_batch.shape
+    y = torch.as_tensor(np.asarray(e_per_site, np.float64) if not isinstance(e_per_site, torch.Tensor)
+                        else e_per_site, dtype=torch.float64).cuda().reshape(-1)
+    ku, lu = np.triu_indices(K, 1)
+    ku_t, lu_t = torch.tensor(ku).cuda(), torch.tensor(lu).cuda()
+    counts = energy_backward_counts(lattice, dims, K, S, occ_batch).to(torch.float64)
+    F = counts[:, :, ku_t, lu_t].reshape(B, -1) / N
+    Fc = F - F.mean(dim=0)
+    L = torch.linalg.cholesky(Fc.T @ Fc / B)
+    A = torch.linalg.inv(L).T
+    theta = torch.zeros(A.shape[1], dtype=torch.float64, device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([theta], lr=lr)
+    sched = torch.optim.lr_scheduler.ExponentialLR(opt, gamma=gamma)
+    fn = EnergyFn()
+    sidx = torch.arange(S, device="cuda")[:, None].expand(S, len(ku))
+
+    def v_of(th):
+        W = (A @ th).reshape(S, -1)
+        V = torch.zeros((S, K, K), dtype=torch.float64, device="cuda")
+        V = V.index_put((sidx, ku_t.expand(S, -1), lu_t.expand(S, -1)), W)
+        return V.index_put((sidx, lu_t.expand(S, -1), ku_t.expand(S, -1)), W)
+
+    yc = y - y.mean()
+    scale = (yc * yc).mean()
+    loss = None
+    for _ in range(steps):
+        opt.zero_grad()
+        e = fn.apply(v_of(theta), occ_batch, lattice, dims) / N
+        r = (e - e.mean()) - yc
+        loss = (r * r).mean() / scale
+        loss.backward()
+        opt.step()
+        sched.step()
+    return v_of(theta.detach()), float(loss.item())
