@@ -35,9 +35,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sweeps-per-step", type=int, default=10)
     ap.add_argument("--edge", type=int, default=800, help="conventional cells per axis")
+    ap.add_argument("--dims", type=str, default="",
+                    help="X,Y,Z conventional cells (overrides --edge; not the headline workload)")
     ap.add_argument("--ell", type=int, default=4, help="link-cell edge")
     ap.add_argument("--tile", type=str, default="0,0,0")
     ap.add_argument("--mode", default="stream", choices=["stream", "persistent", "plain", "auto"])
+    ap.add_argument("--tiles", action="store_true",
+                    help="stage per-offset tile windows even where whole-row windows fit")
     ap.add_argument("--double-buffer", action="store_true",
                     help="stream the next tile window in while the current one runs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -106,7 +110,7 @@ def main():
     from paper_2503_12591_amd import smcx
 
     lattice, K, S = I.BCC, 4, 4
-    dims = (args.edge,) * 3
+    dims = tuple(int(x) for x in args.dims.split(",")) if args.dims else (args.edge,) * 3
     N = I.n_sites(lattice, dims)
     V = I.epi(K, S, 0.02, seed=5)
     T = 1200.0
@@ -116,7 +120,8 @@ def main():
     print(f"[bench] generating {N} sites", file=sys.stderr, flush=True)
     occ = I.occupancy_device(I.equiatomic(K, N), seed=0)
     occ_host = occ.cpu().numpy() if not args.no_cpu_baseline else None
-    lat = smcx.Lattice(lattice, dims, K, S, occ, ell=args.ell, tile=tile, double_buffer=args.double_buffer)
+    lat = smcx.Lattice(lattice, dims, K, S, occ, ell=args.ell, tile=tile, double_buffer=args.double_buffer,
+                       rows=not args.tiles)
     lat.set_epi(V)
     cells, nA = lat.schedule(0)
     nC = int(np.prod([len(c) for c in cells]))
@@ -164,10 +169,13 @@ def main():
     value = attempted / secs
     avg_launch_s = kern_ms / 1e3 / max(launches, 1)
     launches_per_sweep = launches / (args.steps * spst)
+    M = [int(max(c)) for c in cells]
+    kernel = "k_rows" if abs(launches_per_sweep - M[1] * M[2]) < 1e-9 else "k_ministep"
     bytes_per_launch = algorithmic_bytes_per_launch(cells, N, 2, launches_per_sweep)
     achieved = bytes_per_launch / avg_launch_s / 1e9 if args.mode == "stream" else None
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_ministep_bcc{args.edge}_ell{args.ell}.json")
+    dtag = "x".join(str(d) for d in dims) if len(set(dims)) > 1 else str(dims[0])
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{kernel[2:]}_bcc{dtag}_ell{args.ell}.json")
     if os.path.exists(tfile):
         with open(tfile) as f:
             tr = json.load(f)
@@ -186,7 +194,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": f"bcc{args.edge}_k4_s4_T1200_sro10", "lattice": "BCC",
+        "config": {"workload": f"bcc{dtag}_k4_s4_T1200_sro10", "lattice": "BCC",
                    "dims": list(dims), "sites": N, "species": K, "shells": S, "T_K": T,
                    "sweeps_per_step": spst, "link_cell": args.ell, "n_ministeps": nA,
                    "n_cells": nC, "mode": args.mode, "tile": list(tile),
@@ -195,7 +203,7 @@ def main():
                    "near_ties": int(tie_count.item())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": "k_ministep",
+                     "traffic": traffic, "kernel": kernel,
                      "avg_launch_us": avg_launch_s * 1e6, "launches": launches,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "wall_s": wall,

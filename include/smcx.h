@@ -117,6 +117,14 @@ typedef struct {
  * workgroups per CU; both give the same trajectory). */
 #define SMCX_FLAG_DOUBLE_BUFFER 1u
 
+/* desc.flags: in stream mode, stage tiles of link cells for every mini-step
+ * even where whole x-rows would fit.  By default, when every cell edge leaves
+ * room for consecutive offsets to share a window (2*edge > 3 + c_max), all
+ * replicas split the same way and a row of link cells fits one workgroup,
+ * stream mode gives each workgroup whole x-rows and runs all mini-steps with
+ * the same (o_y, o_z) in one launch.  Both give the same trajectory. */
+#define SMCX_FLAG_TILES 2u
+
 int smcx_version(void);
 
 /* Thread-local text of the last error (empty string when none). */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -74,6 +75,7 @@ struct Replica {
     int prow, prows;
     int64_t pad_off, pad_bytes;
     int mult[kMaxShells][kMaxZ1];
+    int rg[2];  // row kernel: row groups along y and z
 };
 
 struct Plan {
@@ -82,6 +84,12 @@ struct Plan {
     int block;  // threads per workgroup: the tile's link cells rounded up to whole waves
     int nbuf;   // window buffers per workgroup
     int group;  // mini-steps of consecutive basis sites sharing one staged window (m, or 1 if an edge < 4)
+    // row kernel (stream mode): lanes = RT[0] cells along x times RT[1] x RT[2] rows
+    bool rows;
+    int RT[3], rblock, rLP, rWY, rWZ;
+    LdsLayout rlds;
+    size_t off_rowoff, off_offP_r, off_offB_r;
+    int64_t total_rowgroups;
     int preset; // compile-time window preset of the stream kernel, or -1
     std::vector<Replica> reps;
     int LP, WY, WZ;
@@ -101,7 +109,7 @@ int make_plan(const smcx_desc* d, Plan& P)
     if (d->n_replicas < 1) return fail(SMCX_E_INVALID_ARG, "n_replicas must be >= 1");
     if (!d->dims) return fail(SMCX_E_INVALID_ARG, "dims is NULL");
     if ((d->ncell == nullptr) != (d->cells == nullptr)) return fail(SMCX_E_INVALID_ARG, "ncell and cells must both be set or both NULL");
-    if (d->flags & ~(uint32_t)SMCX_FLAG_DOUBLE_BUFFER) return fail(SMCX_E_INVALID_ARG, "unknown flags");
+    if (d->flags & ~(uint32_t)(SMCX_FLAG_DOUBLE_BUFFER | SMCX_FLAG_TILES)) return fail(SMCX_E_INVALID_ARG, "unknown flags");
     P.nbuf = (d->flags & SMCX_FLAG_DOUBLE_BUFFER) ? 2 : 1;
     P.lattice = d->lattice;
     P.K = d->n_species;
@@ -254,6 +262,81 @@ int make_plan(const smcx_desc* d, Plan& P)
     const int64_t max_off = 2LL * P.LP * P.WY + 2LL * P.LP + 2 * P.m + 4;
     if (max_off > 32767) return fail(SMCX_E_UNSUPPORTED, "LDS offsets exceed 16 bits; use a smaller tile");
 
+    // row kernel: whole x-rows per workgroup, every o_x of a (o_y, o_z) group
+    // in one launch.  Needs shared windows for all basis sites (P.group), the
+    // same mini-step decomposition in every replica, a row within one block,
+    // and windows no taller than the lattice on y and z (so no site appears
+    // twice in a window except through the x halo).
+    P.rows = false;
+    if (P.group == P.m && P.nbuf == 1 && !(d->flags & SMCX_FLAG_TILES)) {
+        bool same_m = true;
+        int ncx = 0, prow = 0;
+        for (const Replica& R : P.reps) {
+            for (int a = 0; a < 3; ++a) same_m &= R.M[a] == P.reps[0].M[a];
+            ncx = std::max(ncx, (int)R.edges[0].size());
+            prow = std::max(prow, R.prow);
+        }
+        // score: busy lanes per block x waves per CU (12 make up for latency)
+        // x a small penalty when a single workgroup per CU leaves its
+        // staging exposed
+        const int tables = lds_layout(P.lattice, P.K, P.S, P.Z1, P.sumZ, 0, 1).total;
+        double best_score = 0.0;
+        int best_lanes = 0, best_win = 0, best[4] = {0, 0, 0, 0};
+        if (same_m && ncx <= kMaxRowBlock)
+            for (int ry : {1, 2, 4, 8, 16})
+                for (int rz : {1, 2, 4, 8, 16}) {
+                    const int lanes = ncx * ry * rz;
+                    if (lanes > kMaxRowBlock) continue;
+                    int wy = 0, wz = 0;
+                    bool fits = true;
+                    for (const Replica& R : P.reps) {
+                        int wyr = 0, wzr = 0;
+                        const int ncy = (int)R.edges[1].size(), ncz = (int)R.edges[2].size();
+                        for (int c0 = 0; c0 < ncy; c0 += ry)
+                            wyr = std::max(wyr, R.origin[1][std::min(c0 + ry, ncy) - 1] - R.origin[1][c0] + 1 + 2 * kHalo);
+                        for (int c0 = 0; c0 < ncz; c0 += rz)
+                            wzr = std::max(wzr, R.origin[2][std::min(c0 + rz, ncz) - 1] - R.origin[2][c0] + 1 + 2 * kHalo);
+                        fits &= wyr <= R.L[1] && wzr <= R.L[2];
+                        wy = std::max(wy, wyr);
+                        wz = std::max(wz, wzr);
+                    }
+                    const int winb = prow * wy * wz;
+                    if (!fits || 2LL * prow * wy + 2LL * prow + 2 * P.m + 4 > 32767) continue;
+                    const int lds = tables + ((winb + 15) & ~15);
+                    if (lds > 160 * 1024) continue;
+                    const int block = (lanes + 63) / 64 * 64;
+                    const int waves = block / 64;
+                    const int wave_cap = block <= kBlock ? 12 : 16;  // register budget of the instantiation
+                    const int wgs = std::min(160 * 1024 / lds, wave_cap / waves);
+                    if (wgs < 1) continue;
+                    const double score = (double)lanes / block * std::min(1.0, wgs * waves / 12.0) *
+                                         (wgs == 1 ? 0.92 : 1.0);
+                    if (score > best_score + 1e-12 || (std::fabs(score - best_score) <= 1e-12 && winb < best_win)) {
+                        best_score = score;
+                        best_lanes = lanes;
+                        best_win = winb;
+                        best[0] = ry; best[1] = rz; best[2] = wy; best[3] = wz;
+                    }
+                }
+        if (best_lanes > 0) {
+            P.rows = true;
+            P.RT[0] = ncx;
+            P.RT[1] = best[0];
+            P.RT[2] = best[1];
+            P.rblock = (best_lanes + 63) / 64 * 64;
+            P.rLP = prow;
+            P.rWY = best[2];
+            P.rWZ = best[3];
+            P.rlds = lds_layout(P.lattice, P.K, P.S, P.Z1, P.sumZ, best_win, 1);
+            P.total_rowgroups = 0;
+            for (Replica& R : P.reps) {
+                R.rg[0] = ((int)R.edges[1].size() + P.RT[1] - 1) / P.RT[1];
+                R.rg[1] = ((int)R.edges[2].size() + P.RT[2] - 1) / P.RT[2];
+                P.total_rowgroups += (int64_t)R.rg[0] * R.rg[1];
+            }
+        }
+    }
+
     // workspace layout
     size_t o = 0;
     P.off_reps = o; o = align256(o + sizeof(RepDev) * P.R);
@@ -267,6 +350,9 @@ int make_plan(const smcx_desc* d, Plan& P)
     P.off_pd = o; o = align256(o + 4 * P.m * P.Z1);
     P.off_D = o; o = align256(o + sizeof(double) * P.K * P.K * P.S * P.K);
     P.off_misc = o; o = align256(o + 256);
+    P.off_rowoff = o; o = align256(o + sizeof(int64_t) * (P.R + 1));
+    P.off_offP_r = o; o = align256(o + sizeof(int16_t) * P.m * P.Z1 * P.sumZ);
+    P.off_offB_r = o; o = align256(o + sizeof(int32_t) * P.m * P.Z1);
     P.off_pad = o;
     P.total_tiles = 0;
     for (Replica& R : P.reps) {
@@ -278,11 +364,12 @@ int make_plan(const smcx_desc* d, Plan& P)
     return SMCX_OK;
 }
 
-// LDS offset of the site at half-unit vector v from a basis-b site.
-int lds_offset(const Plan& P, int b, int vx, int vy, int vz)
+// LDS offset of the site at half-unit vector v from a basis-b site in a
+// window of row pitch LP and WY rows per plane.
+int lds_offset(const Plan& P, int LP, int WY, int b, int vx, int vy, int vz)
 {
     const Nb nb = nb_of(kGeom[P.lattice], b, vx, vy, vz);
-    return nb.dz * P.LP * P.WY + nb.dy * P.LP + P.m * nb.dx + (nb.bt - b);
+    return nb.dz * LP * WY + nb.dy * LP + P.m * nb.dx + (nb.bt - b);
 }
 
 }  // namespace
@@ -303,6 +390,8 @@ struct smcx_lattice {
     int stream_wgs = 8;  // stream-mode grid: 8 XCD chunks x workgroups per XCD
     const void* k_stream = nullptr;
     const void* k_persistent = nullptr;
+    const void* k_rows = nullptr;
+    int rows_wgs = 8;
 };
 
 namespace {
@@ -341,6 +430,29 @@ SweepArgs base_args(smcx_lattice* h)
     return a;
 }
 
+// Launch arguments of the row kernel: row windows, their offset tables and
+// the prefix sums of row groups per replica.
+SweepArgs row_args(smcx_lattice* h)
+{
+    const Plan& P = h->P;
+    SweepArgs a = base_args(h);
+    a.tile_off = (const int64_t*)(h->ws + P.off_rowoff);
+    a.offP = (const int16_t*)(h->ws + P.off_offP_r);
+    a.offB = (const int32_t*)(h->ws + P.off_offB_r);
+    for (int i = 0; i < 3; ++i) a.T[i] = P.RT[i];
+    a.LP = P.rLP;
+    a.WY = P.rWY;
+    a.WZ = P.rWZ;
+    a.lds_d = P.rlds.d_off;
+    a.lds_offp = P.rlds.offp_off;
+    a.lds_offb = P.rlds.offb_off;
+    a.lds_pd = P.rlds.pd_off;
+    a.lds_win = P.rlds.win_off;
+    a.win_bytes = P.rlds.win_bytes;
+    a.nbuf = 1;
+    return a;
+}
+
 hipEvent_t take_event(smcx_lattice* h)
 {
     if (!h->pool.empty()) {
@@ -353,7 +465,8 @@ hipEvent_t take_event(smcx_lattice* h)
     return e;
 }
 
-int timed_launch(smcx_lattice* h, bool persistent, dim3 grid, hipStream_t st, const SweepArgs& a)
+int timed_launch(smcx_lattice* h, const void* kernel, dim3 grid, int block, size_t lds, hipStream_t st,
+                 const SweepArgs& a)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->timing) {
@@ -362,7 +475,7 @@ int timed_launch(smcx_lattice* h, bool persistent, dim3 grid, hipStream_t st, co
         if (!e0 || !e1) return fail(SMCX_E_HIP, "hipEventCreate failed");
         SMCX_HIP(hipEventRecord(e0, st));
     }
-    SMCX_HIP(launch_sweep(persistent ? h->k_persistent : h->k_stream, grid, h->P.block, h->P.lds.total, st, a));
+    SMCX_HIP(launch_sweep(kernel, grid, block, lds, st, a));
     if (h->timing) {
         SMCX_HIP(hipEventRecord(e1, st));
         h->pending.emplace_back(e0, e1);
@@ -468,28 +581,40 @@ int smcx_lattice_init(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_de
         tile_off[r + 1] = tile_off[r] + R.ntiles;
     }
     const Geometry& G = kGeom[P.lattice];
-    std::vector<int16_t> offP((size_t)P.m * P.Z1 * P.sumZ);
-    std::vector<int32_t> offB((size_t)P.m * P.Z1);
+    std::vector<int16_t> offP((size_t)P.m * P.Z1 * P.sumZ), offP_r(offP.size());
+    std::vector<int32_t> offB((size_t)P.m * P.Z1), offB_r(offB.size());
     std::vector<int8_t> pd((size_t)4 * P.m * P.Z1);
     for (int b = 0; b < P.m; ++b)
         for (int k = 0; k < P.Z1; ++k) {
             const int* d1 = G.v[0][k];
-            offB[b * P.Z1 + k] = lds_offset(P, b, d1[0], d1[1], d1[2]);
+            offB[b * P.Z1 + k] = lds_offset(P, P.LP, P.WY, b, d1[0], d1[1], d1[2]);
+            if (P.rows) offB_r[b * P.Z1 + k] = lds_offset(P, P.rLP, P.rWY, b, d1[0], d1[1], d1[2]);
             const Nb nb = nb_of(G, b, d1[0], d1[1], d1[2]);
             int8_t* q = &pd[(b * P.Z1 + k) * 4];
             q[0] = (int8_t)nb.dx; q[1] = (int8_t)nb.dy; q[2] = (int8_t)nb.dz; q[3] = (int8_t)nb.bt;
             int j = 0;
             for (int s = 0; s < P.S; ++s)
-                for (int n = 0; n < G.Z[s]; ++n, ++j)
-                    offP[(b * P.Z1 + k) * P.sumZ + j] =
-                        (int16_t)lds_offset(P, b, d1[0] + G.v[s][n][0], d1[1] + G.v[s][n][1], d1[2] + G.v[s][n][2]);
+                for (int n = 0; n < G.Z[s]; ++n, ++j) {
+                    const int vx = d1[0] + G.v[s][n][0], vy = d1[1] + G.v[s][n][1], vz = d1[2] + G.v[s][n][2];
+                    offP[(b * P.Z1 + k) * P.sumZ + j] = (int16_t)lds_offset(P, P.LP, P.WY, b, vx, vy, vz);
+                    if (P.rows) offP_r[(b * P.Z1 + k) * P.sumZ + j] = (int16_t)lds_offset(P, P.rLP, P.rWY, b, vx, vy, vz);
+                }
         }
+    std::vector<int64_t> row_off(P.R + 1, 0);
+    for (int r = 0; r < P.R; ++r) {
+        reps[r].rg[0] = P.rows ? P.reps[r].rg[0] : 0;
+        reps[r].rg[1] = P.rows ? P.reps[r].rg[1] : 0;
+        row_off[r + 1] = row_off[r] + (int64_t)reps[r].rg[0] * reps[r].rg[1];
+    }
     SMCX_HIP(hipMemcpyAsync(h->ws + P.off_reps, reps.data(), sizeof(RepDev) * P.R, hipMemcpyHostToDevice, st));
     SMCX_HIP(hipMemcpyAsync(h->ws + P.off_origins, origins.data(), sizeof(int32_t) * origins.size(), hipMemcpyHostToDevice, st));
     SMCX_HIP(hipMemcpyAsync(h->ws + P.off_tileoff, tile_off.data(), sizeof(int64_t) * tile_off.size(), hipMemcpyHostToDevice, st));
     SMCX_HIP(hipMemcpyAsync(h->ws + P.off_offP, offP.data(), sizeof(int16_t) * offP.size(), hipMemcpyHostToDevice, st));
     SMCX_HIP(hipMemcpyAsync(h->ws + P.off_offB, offB.data(), sizeof(int32_t) * offB.size(), hipMemcpyHostToDevice, st));
     SMCX_HIP(hipMemcpyAsync(h->ws + P.off_pd, pd.data(), pd.size(), hipMemcpyHostToDevice, st));
+    SMCX_HIP(hipMemcpyAsync(h->ws + P.off_rowoff, row_off.data(), sizeof(int64_t) * row_off.size(), hipMemcpyHostToDevice, st));
+    SMCX_HIP(hipMemcpyAsync(h->ws + P.off_offP_r, offP_r.data(), sizeof(int16_t) * offP_r.size(), hipMemcpyHostToDevice, st));
+    SMCX_HIP(hipMemcpyAsync(h->ws + P.off_offB_r, offB_r.data(), sizeof(int32_t) * offB_r.size(), hipMemcpyHostToDevice, st));
     int32_t* bad = (int32_t*)(h->ws + P.off_misc);
     SMCX_HIP(launch_fill_i32(bad, 1, 0, st));
     SMCX_HIP(launch_validate(occ_dev, P.total_sites, P.K, bad, st));
@@ -514,6 +639,13 @@ int smcx_lattice_init(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_de
     SMCX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     SMCX_HIP(sweep_occupancy(h->k_stream, P.block, P.lds.total, &per_cu));
     h->stream_wgs = 8 * std::max(1, (cus / 8) * std::max(1, per_cu));
+    if (P.rows) {
+        h->k_rows = row_kernel(P.lattice, P.K, P.S, P.rblock);
+        SMCX_HIP(set_sweep_lds_limit(h->k_rows, P.rlds.total));
+        int rcu = 1;
+        SMCX_HIP(sweep_occupancy(h->k_rows, P.rblock, P.rlds.total, &rcu));
+        h->rows_wgs = 8 * std::max(1, (cus / 8) * std::max(1, rcu));
+    }
     *out = h;
     g_err.clear();
     return SMCX_OK;
@@ -612,7 +744,29 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
         a.beta = beta_dev;
         a.beta_stride = P.R;
         a.nb = P.group;
-        if (int rc = timed_launch(h, true, dim3(P.R), st, a)) return rc;
+        if (int rc = timed_launch(h, h->k_persistent, dim3(P.R), P.block, P.lds.total, st, a)) return rc;
+    } else if (mode == SMCX_MODE_STREAM && P.rows) {
+        // one launch per (o_y, o_z) group: every o_x and basis site
+        SweepArgs ra = row_args(h);
+        ra.seed = a.seed;
+        ra.stats = a.stats;
+        ra.ties = a.ties;
+        ra.tie_cap = a.tie_cap;
+        ra.tie_count = a.tie_count;
+        const int G = P.m * P.reps[0].M[0];
+        const dim3 grid((unsigned)std::min<int64_t>(h->rows_wgs, 8 * ((P.total_rowgroups + 7) / 8)));
+        for (int js = 0; js < n_sweeps; ++js) {
+            ra.first_sweep = first_sweep + (uint32_t)js;
+            ra.beta = beta_dev + (int64_t)js * P.R;
+            const int end = std::min(tau_end, P.max_nA);
+            for (int g = tau_begin; g < end;) {
+                const int ge = std::min(end, (g / G + 1) * G);
+                ra.g = g;
+                ra.nb = ge - g;
+                if (int rc = timed_launch(h, h->k_rows, grid, P.rblock, P.rlds.total, st, ra)) return rc;
+                g = ge;
+            }
+        }
     } else if (mode == SMCX_MODE_STREAM) {
         const dim3 grid((unsigned)std::min<int64_t>(h->stream_wgs, 8 * ((P.total_tiles + 7) / 8)));
         for (int js = 0; js < n_sweeps; ++js) {
@@ -622,7 +776,7 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
             for (int g = tau_begin; g < end; g = group_end(g, end)) {
                 a.g = g;
                 a.nb = group_end(g, end) - g;
-                if (int rc = timed_launch(h, false, grid, st, a)) return rc;
+                if (int rc = timed_launch(h, h->k_stream, grid, P.block, P.lds.total, st, a)) return rc;
             }
         }
     } else {
@@ -636,7 +790,7 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
                 for (int g = tau_begin; g < end; g = group_end(g, end)) {
                     a.g = g;
                     a.nb = group_end(g, end) - g;
-                    if (int rc = timed_launch(h, false, grid, st, a)) return rc;
+                    if (int rc = timed_launch(h, h->k_stream, grid, P.block, P.lds.total, st, a)) return rc;
                 }
             }
         }

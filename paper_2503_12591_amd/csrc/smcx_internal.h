@@ -20,6 +20,7 @@ constexpr int kMaxK = 8;
 constexpr int kMaxZ1 = 12;
 constexpr int kMaxSumZ = 54;
 constexpr int kBlock = 256;
+constexpr int kMaxRowBlock = 1024;  // row kernel: several x-rows of link cells per workgroup
 
 // ---------------------------------------------------------------------------
 // Geometry.  Positions are in half lattice constants.  Coordination shells are
@@ -141,6 +142,7 @@ struct RepDev {
     int32_t prow;        // padded row pitch (bytes, multiple of 16)
     int32_t prows;       // rows per padded plane (L1 + 2H)
     int32_t alias;       // some partner has images in another shell (an edge of 2)
+    int32_t rg[2];       // row kernel: groups of rows along y and z
     int64_t pad_off;     // byte offset of the padded copy in the workspace
     int64_t occ_off;     // first site of this replica in the occupancy array
     int64_t N;           // sites

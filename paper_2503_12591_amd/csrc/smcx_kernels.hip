@@ -39,6 +39,9 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
                                               uint32_t k0, uint32_t k1, uint32_t& o0,
                                               uint32_t& o1, uint32_t& o2, uint32_t& o3)
 {
+    // the key is wave-uniform: keep it in scalar registers and let the round
+    // keys be formed here, not hoisted out of the trial loops as 20 live SGPRs
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
@@ -213,6 +216,7 @@ __device__ void load_tables(const SweepArgs& A, uint8_t* smem)
 // ---------------------------------------------------------------------------
 struct GeoRt {
     static constexpr bool fixed = false;
+    static constexpr bool rows = false;
     static constexpr int ELL = 0;
     __device__ static int T(const SweepArgs& A, int a) { return A.T[a]; }
     __device__ static int LP(const SweepArgs& A) { return A.LP; }
@@ -228,6 +232,7 @@ struct GeoFix {
     static constexpr Preset P = kPresets[PI];
     static_assert(preset_ok(P), "tile start must be 16-byte aligned");
     static constexpr bool fixed = true;
+    static constexpr bool rows = false;
     static constexpr int ELL = P.ell;
     static constexpr int kLP = preset_LP(P), kWY = preset_WY(P), kWZ = preset_WZ(P);
     static constexpr int kBLOCK = (P.tx * P.ty * P.tz + 63) / 64 * 64;
@@ -238,6 +243,17 @@ struct GeoFix {
     __device__ static constexpr int block(const SweepArgs&) { return (P.tx * P.ty * P.tz + 63) / 64 * 64; }
     __device__ static constexpr int K(const SweepArgs&) { return P.K; }
     __device__ static constexpr int S(const SweepArgs&) { return P.S; }
+};
+
+// Row windows: the window holds whole padded x-rows (periodic images of the
+// sites within two cells of the x faces included), so a written site must be
+// copied to its image in the window too.  KK / SS fix the species and shell
+// counts at compile time (0: taken from the launch).
+template <int KK, int SS>
+struct GeoRow : GeoRt {
+    static constexpr bool rows = true;
+    __device__ static int K(const SweepArgs& A) { return KK ? KK : A.K; }
+    __device__ static int S(const SweepArgs& A) { return SS ? SS : A.S; }
 };
 
 struct TileGeom {
@@ -501,6 +517,7 @@ __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& re
         const int8_t* pd = T.pd + (L.b * Z1 + k) * 4;
         int bx = L.ax + pd[0], by = L.ay + pd[1], bz = L.az + pd[2];
         const int bb = pd[3];
+        const int ubx = bx;  // partner x before the periodic wrap (its column in a row window)
         bx += bx < 0 ? rep.L[0] : (bx >= rep.L[0] ? -rep.L[0] : 0);
         by += by < 0 ? rep.L[1] : (by >= rep.L[1] ? -rep.L[1] : 0);
         bz += bz < 0 ? rep.L[2] : (bz >= rep.L[2] ? -rep.L[2] : 0);
@@ -510,6 +527,14 @@ __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& re
         store_site(pad, rep, m, bx, by, bz, bb, (uint8_t)p8);
         win[L.la] = (uint8_t)q8;
         win[L.lb] = (uint8_t)p8;
+        if constexpr (Geo::rows) {
+            // row windows span x in [-H, L + H): sites within H of an x face appear twice
+            const int Lx = rep.L[0], sh = m * Lx;
+            if (L.ax < kHalo) win[L.la + sh] = (uint8_t)q8;
+            if (L.ax >= Lx - kHalo) win[L.la - sh] = (uint8_t)q8;
+            if (ubx < kHalo) win[L.lb + sh] = (uint8_t)p8;
+            if (ubx >= Lx - kHalo) win[L.lb - sh] = (uint8_t)p8;
+        }
     }
     return 1 | (acc ? 2 : 0) | (tie ? 4 : 0);
 }
@@ -807,6 +832,114 @@ __global__ __launch_bounds__(kBlock) void k_ministep(SweepArgs A)
 }
 
 // ---------------------------------------------------------------------------
+// Row mode: one launch per group of mini-steps sharing the offsets (o_y, o_z)
+// -- every o_x and basis site, M_x * m mini-steps.  A workgroup owns whole
+// x-rows of link cells (T[1] x T[2] rows of every cell along x) and stages
+// their window once: full padded x-rows, y and z within two cells of the
+// active rows.  Within the group a trial depends only on trials of the same
+// row (cells in other rows stay beyond the reach on y or z, since o_y and o_z
+// are fixed), and there only on earlier offsets o_x; a workgroup barrier after
+// each o_x orders them.  Accepted swaps go to HBM, to the window and to the
+// window's x-images, so every later trial of the group reads them from LDS.
+// A launch covers mini-steps g .. g + nb - 1 of one group.  MAXB: the largest
+// workgroup the instantiation serves (1024 caps registers at 4 waves/SIMD).
+// ---------------------------------------------------------------------------
+template <int LAT, int E, class Geo, int MAXB>
+__global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
+{
+    constexpr int m = kGeom[LAT].m;
+    extern __shared__ __align__(16) uint8_t smem[];
+    load_tables<LAT>(A, smem);
+    const Lds T = lds_ptrs(A, smem);
+    uint8_t* win = smem + A.lds_win;
+    const int64_t total = ld_const(A.tile_off, A.R);  // row groups of all replicas
+    const int xcd = blockIdx.x % 8;
+    const int64_t W = gridDim.x / 8;
+    const int64_t chunk = (total + 7) / 8;
+    const int64_t lo = xcd * chunk;
+    const int64_t hi = min(lo + chunk, total);
+    const int l = threadIdx.x;
+    const int lx = l % A.T[0], ly = (l / A.T[0]) % A.T[1], lz = l / (A.T[0] * A.T[1]);
+    const uint32_t t = A.first_sweep;
+    Stats st;
+    int r_stats = -1;
+    for (int64_t i = lo + blockIdx.x / 8; i < hi; i += W) {
+        int a = 0, z = A.R - 1;  // last replica with tile_off[r] <= i
+        while (a < z) {
+            const int mid = (a + z + 1) >> 1;
+            if (ld_const(A.tile_off, mid) <= i) a = mid; else z = mid - 1;
+        }
+        int r = a;
+        int64_t grp = i - ld_const(A.tile_off, a);
+        uniform(r, grp);
+        const RepDev& rep = rep_of(A, r);
+        if (A.g >= rep.nA) continue;
+        const int b0 = A.g % m, rest = A.g / m;
+        const int ox0 = rest % rep.M[0];
+        const int oy = (rest / rep.M[0]) % rep.M[1], oz = rest / (rep.M[0] * rep.M[1]);
+        const int gy = (int)(grp % rep.rg[0]), gz = (int)(grp / rep.rg[0]);
+        TileGeom tg;
+        tg.c0[0] = 0;
+        tg.c1[0] = rep.nc[0];
+        tg.c0[1] = gy * A.T[1];
+        tg.c1[1] = min(tg.c0[1] + A.T[1], rep.nc[1]);
+        tg.c0[2] = gz * A.T[2];
+        tg.c1[2] = min(tg.c0[2] + A.T[2], rep.nc[2]);
+        tg.w0[0] = -kHalo;
+        tg.n[0] = rep.L[0] + 2 * kHalo;
+        tg.gx0 = 0;
+        const int oo[3] = {0, oy, oz};
+#pragma unroll
+        for (int ax = 1; ax < 3; ++ax) {
+            tg.w0[ax] = cell_origin<Geo>(A, rep, ax, tg.c0[ax]) + oo[ax] - kHalo;
+            const int w1 = min(cell_origin<Geo>(A, rep, ax, tg.c1[ax] - 1) + oo[ax] + kHalo + 1, rep.L[ax] + kHalo);
+            tg.n[ax] = w1 - tg.w0[ax];
+        }
+        if (tg.n[1] <= 0 || tg.n[2] <= 0) continue;
+        lds_barrier();  // every lane is done with the previous window
+        stage_async<LAT, Geo>(A, rep, tg, A.ws + rep.pad_off, win);
+        // this lane's cell while the loads fly
+        const int cx = lx, cy = tg.c0[1] + ly, cz = tg.c0[2] + lz;
+        const bool in = lz < A.T[2] && cx < tg.c1[0] && cy < tg.c1[1] && cz < tg.c1[2];
+        int x0 = 0, ex = 0, y0 = 0, ey = 0, z0 = 0, ez = 0;
+        if (in) {
+            x0 = cell_origin<Geo>(A, rep, 0, cx);
+            ex = cell_origin<Geo>(A, rep, 0, cx + 1) - x0;
+            y0 = cell_origin<Geo>(A, rep, 1, cy);
+            ey = cell_origin<Geo>(A, rep, 1, cy + 1) - y0;
+            z0 = cell_origin<Geo>(A, rep, 2, cz);
+            ez = cell_origin<Geo>(A, rep, 2, cz + 1) - z0;
+        }
+        const bool yz = in && oy < ey && oz < ez;
+        const double beta = ld_const(A.beta, r);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (r != r_stats) {
+            flush_stats(A, r_stats, st);
+            r_stats = r;
+        }
+        int tau = A.g, b = b0, ox = ox0;
+        const int tau1 = A.g + A.nb;
+        while (true) {
+            const int nbb = min(m - b, tau1 - tau);
+            if (yz && ox < ex) {
+                for (int j = 0; j < nbb; ++j) {
+                    LaneState<E> L;
+                    read_dispatch<LAT, E, Geo>(b + j, A, rep, T, win, tg, r, t, x0 + ox, y0 + oy, z0 + oz, L);
+                    tile_finish<LAT, E, Geo>(A, rep, r, t, beta, T, win, L, st);
+                }
+            }
+            tau += nbb;
+            if (tau >= tau1) break;
+            b = 0;
+            ++ox;
+            __syncthreads();  // the next offset's trials read what this one wrote
+        }
+    }
+    flush_stats(A, r_stats, st);
+}
+
+// ---------------------------------------------------------------------------
 // Persistent mode: one workgroup per replica runs every sweep and mini-step;
 // block barriers order the mini-steps (all writes of a replica come from its
 // own workgroup, and a barrier makes them visible to its later loads).
@@ -1033,6 +1166,34 @@ static const void* persistent_kernel()
     return (const void*)k_persistent<LAT, E, GeoRt>;
 }
 
+
+// Row kernels: compile-time species / shell counts for the 4-species BCC and
+// 5-species FCC alloys with 4 shells, runtime counts otherwise.
+template <int LAT, int E, int MAXB>
+static const void* row_kernel_e(int K, int S)
+{
+    if constexpr (LAT == SMCX_BCC && E == 1)
+        if (K == 4 && S == 4) return (const void*)k_rows<LAT, E, GeoRow<4, 4>, MAXB>;
+    if constexpr (LAT == SMCX_FCC && E == 3)
+        if (K == 5 && S == 4) return (const void*)k_rows<LAT, E, GeoRow<5, 4>, MAXB>;
+    return (const void*)k_rows<LAT, E, GeoRow<0, 0>, MAXB>;
+}
+
+template <int MAXB>
+static const void* row_kernel_b(int lattice, int K, int S)
+{
+    const int e = encoding_of(K);
+    if (lattice == SMCX_BCC)
+        return e == 1 ? row_kernel_e<SMCX_BCC, 1, MAXB>(K, S)
+                      : (e == 3 ? row_kernel_e<SMCX_BCC, 3, MAXB>(K, S) : row_kernel_e<SMCX_BCC, 2, MAXB>(K, S));
+    return e == 1 ? row_kernel_e<SMCX_FCC, 1, MAXB>(K, S)
+                  : (e == 3 ? row_kernel_e<SMCX_FCC, 3, MAXB>(K, S) : row_kernel_e<SMCX_FCC, 2, MAXB>(K, S));
+}
+
+const void* row_kernel(int lattice, int K, int S, int block)
+{
+    return block <= kBlock ? row_kernel_b<kBlock>(lattice, K, S) : row_kernel_b<kMaxRowBlock>(lattice, K, S);
+}
 
 const void* sweep_kernel(int lattice, int K, bool persistent, int preset, int nbuf)
 {

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsmcx.so")
 BCC, FCC = 0, 1
 MODE_AUTO, MODE_STREAM, MODE_PERSISTENT, MODE_PLAIN = 0, 1, 2, 3
 FLAG_DOUBLE_BUFFER = 1
+FLAG_TILES = 2
 MODES = {"auto": MODE_AUTO, "stream": MODE_STREAM, "persistent": MODE_PERSISTENT, "plain": MODE_PLAIN}
 TIE_DTYPE = np.dtype([("replica", "<i4"), ("sweep", "<u4"), ("site", "<i8"), ("decision", "<i4"),
                       ("pad", "<i4")])
@@ -118,7 +119,7 @@ class Lattice:
     """
 
     def __init__(self, lattice: int, dims, K: int, S: int, occ, ell=None, cells=None,
-                 tile=(0, 0, 0), double_buffer: bool = False):
+                 tile=(0, 0, 0), double_buffer: bool = False, rows: bool = True):
         torch = _torch()
         self.torch = torch
         dims = np.asarray(dims, dtype=np.int32).reshape(-1, 3)
@@ -153,7 +154,7 @@ class Lattice:
             d.ncell, d.cells = p1, p2
         for a in range(3):
             d.tile[a] = int(tile[a])
-        d.flags = FLAG_DOUBLE_BUFFER if double_buffer else 0
+        d.flags = (FLAG_DOUBLE_BUFFER if double_buffer else 0) | (0 if rows else FLAG_TILES)
         self._desc = d
         nbytes = C.c_size_t(0)
         _check(lib().smcx_workspace_size(C.byref(d), C.byref(nbytes)))

@@ -28,14 +28,14 @@ def rand_occ(N, K, seed, equi=True):
 
 
 def gpu_vs_oracle(lattice, dims, K, S, occ0, V, betas, seed=0, mode="auto", ell=None, cells=None,
-                  tile=(0, 0, 0), first_sweep=0, check_every_sweep=False):
+                  tile=(0, 0, 0), first_sweep=0, check_every_sweep=False, rows=True):
     """Run len(betas) sweeps on the GPU and in the oracle; assert equality of
     the occupancy, attempted/accepted counts and near-tie counts."""
     from paper_2503_12591_amd import smcx
     say(f"sweep lattice={lattice} dims={tuple(dims)} K={K} S={S} n={len(betas)} mode={mode} "
-        f"ell={ell} tile={tile} seed={seed}")
+        f"ell={ell} tile={tile} seed={seed} rows={rows}")
     lat = smcx.Lattice(lattice, dims, K, S, occ0, ell=ell,
-                       cells=None if cells is None else [cells], tile=tile)
+                       cells=None if cells is None else [cells], tile=tile, rows=rows)
     lat.set_epi(V)
     sched, nA = lat.schedule(0)
     if cells is not None:

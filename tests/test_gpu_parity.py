@@ -121,6 +121,101 @@ def test_trajectories_varied_geometry(smcx, lattice, dims, K, S, ell, tile, mode
                   first_sweep=3)
 
 
+@pytest.mark.parametrize("rows", [True, False])
+@pytest.mark.parametrize("lattice,dims,K,S,ell", [
+    (BCC, (16, 12, 20), 4, 4, 4),
+    (BCC, (17, 13, 9), 4, 4, 4),      # uneven cells 4/5
+    (BCC, (40, 8, 8), 4, 4, 4),       # ten cells along x, x-images in the window
+    (FCC, (9, 8, 10), 5, 4, 3),       # 6-bit counters
+    (BCC, (12, 9, 10), 4, 2, 3),      # two shells
+    (FCC, (12, 12, 12), 3, 3, 4),
+])
+def test_stream_rows_and_tiles(smcx, lattice, dims, K, S, ell, rows):
+    """Stream mode with whole-row windows (all offsets o_x of a group in one
+    launch) and with per-mini-step tile windows: both equal the oracle."""
+    N = int(np.prod(dims)) * (2 if lattice == BCC else 4)
+    occ = rand_occ(N, K, 7 * sum(dims))
+    V = sym_V(S, K, 0.04, 3 * K + S)
+    betas = I.beta_of_T(np.linspace(2000, 500, 5))
+    gpu_vs_oracle(lattice, dims, K, S, occ, V, betas, seed=4242, mode="stream", ell=ell,
+                  first_sweep=11, rows=rows)
+
+
+@pytest.mark.parametrize("lattice,dims,K,S,ell,rows,per_sweep", [
+    (BCC, (16, 12, 20), 4, 4, 4, True, 16),    # one launch per (o_y, o_z)
+    (BCC, (16, 12, 20), 4, 4, 4, False, 64),   # one per offset, basis sites sharing it
+    (BCC, (12, 12, 12), 4, 4, 3, True, 54),    # 2*3 <= 3 + 3: one mini-step per launch
+    (BCC, (8, 8, 8), 4, 2, 4, True, 16),
+])
+def test_stream_launch_structure(smcx, lattice, dims, K, S, ell, rows, per_sweep):
+    """The launches a sweep takes show which window scheme ran."""
+    N = int(np.prod(dims)) * (2 if lattice == BCC else 4)
+    lat = smcx.Lattice(lattice, dims, K, S, rand_occ(N, K, 3), ell=ell, rows=rows)
+    lat.set_epi(sym_V(S, K, 0.03, 2))
+    lat.timing(True)
+    lat.timing_read()
+    lat.sweep(2, 0, I.beta_of_T([900.0, 900.0]), mode="stream")
+    _, launches = lat.timing_read()
+    lat.close()
+    assert launches == 2 * per_sweep
+
+
+def test_stream_rows_partial_ranges(smcx):
+    """Mini-step ranges that cut row groups (inside an o_x run and between
+    basis sites) compose to the full sweep."""
+    from paper_2503_12591_amd import smcx as S
+    dims, K, Sh = (16, 12, 12), 4, 4
+    occ0 = rand_occ(2 * 16 * 12 * 12, K, 31)
+    V = sym_V(Sh, K, 0.04, 8)
+    b = I.beta_of_T([1100.0])
+    say("row partial ranges")
+    full = S.Lattice(BCC, dims, K, Sh, occ0, ell=4)
+    full.set_epi(V)
+    full.sweep(1, 5, b, first_sweep=2, mode="stream")
+    parts = S.Lattice(BCC, dims, K, Sh, occ0, ell=4)
+    parts.set_epi(V)
+    _, nA = parts.schedule(0)
+    for lo, hi in [(0, 3), (3, 8), (8, 13), (13, 40), (40, 41), (41, nA)]:
+        parts.sweep_partial(2, lo, hi, 5, b, mode="stream")
+    assert np.array_equal(full.occupancy(), parts.occupancy())
+    cells, _ = full.schedule(0)
+    ref = occ0.copy()
+    O.run(BCC, dims, K, Sh, cells, ref, V, 5, b, first_sweep=2)
+    assert np.array_equal(full.occupancy(), ref)
+    full.close()
+    parts.close()
+
+
+def test_stream_rows_multi_replica(smcx):
+    """Replicas of different shapes with the same mini-step decomposition run
+    in one row launch per group."""
+    from paper_2503_12591_amd import smcx as S
+    dims = np.array([[16, 16, 16], [20, 16, 12], [12, 24, 16]], np.int32)
+    K, Sh = 4, 4
+    occs = [rand_occ(int(2 * np.prod(d)), K, 50 + r) for r, d in enumerate(dims)]
+    V = sym_V(Sh, K, 0.03, 21)
+    betas = I.beta_of_T(np.array([500.0, 1200.0, 3000.0]))
+    n = 3
+    say("rows multi-replica")
+    lat = S.Lattice(BCC, dims, K, Sh, np.concatenate(occs), ell=4)
+    lat.set_epi(V)
+    bt = np.tile(betas, (n, 1))
+    stats, ties, tc = lat.sweep(n, 9, bt, mode="stream")
+    gpu = lat.occupancy()
+    tnp, _ = lat.ties_to_numpy(ties, tc)
+    s = stats.cpu().numpy().reshape(-1, 3)
+    off = 0
+    for r in range(len(dims)):
+        cells, _ = lat.schedule(r)
+        ref = occs[r].copy()
+        res = O.run(BCC, dims[r], K, Sh, cells, ref, V, 9, bt[:, r], replica=r,
+                    replay=tnp[tnp["replica"] == r])
+        assert np.array_equal(gpu[off:off + len(ref)], ref), f"replica {r}"
+        assert s[r, 0] == res.stats[0] and s[r, 1] == res.stats[1]
+        off += len(ref)
+    lat.close()
+
+
 def test_explicit_partition(smcx):
     dims = (12, 10, 9)
     cells = [np.array([3, 5, 4]), np.array([4, 3, 3]), np.array([9])]
