@@ -159,7 +159,7 @@ int smcx_get_schedule(const smcx_lattice *h, int32_t replica, int32_t *ncell_out
                       int32_t *cells_out, int32_t *n_ministeps);
 
 /* Set the EPI tensor V (host, binary64, [S][K][K], eV).  V must be symmetric
- * in (k, l) exactly.  Tables D[p][q][s][t] = V_s[q][t] - V_s[p][t] are uploaded
+ * in (k, l) exactly.  Tables D[s][t][p][q] = V_s[q][t] - V_s[p][t] are uploaded
  * on `stream`, which is synchronised. */
 int smcx_set_epi(smcx_lattice *h, const double *V, void *stream);
 

@@ -73,6 +73,7 @@ struct Replica {
     int ntile[3];
     int64_t ntiles;
     int prow, prows;
+    int cp, prowp;  // basis-planar rows: column pitch and row pitch
     int64_t pad_off, pad_bytes;
     int mult[kMaxShells][kMaxZ1];
     int rg[2];  // row kernel: row groups along y and z
@@ -193,8 +194,11 @@ int make_plan(const smcx_desc* d, Plan& P)
         P.max_nA = std::max(P.max_nA, R.nA);
         R.ntiles = (int64_t)R.ntile[0] * R.ntile[1] * R.ntile[2];
         R.prow = (P.m * (R.L[0] + 2 * kHalo) + 15) & ~15;
+        R.cp = (R.L[0] + 2 * kHalo + 15) & ~15;
+        R.prowp = P.m * R.cp;
         R.prows = R.L[1] + 2 * kHalo;
-        R.pad_bytes = (int64_t)R.prow * R.prows * (R.L[2] + 2 * kHalo);
+        // one region serves both layouts (a sweep call packs the one its kernels read)
+        R.pad_bytes = (int64_t)std::max(R.prow, R.prowp) * R.prows * (R.L[2] + 2 * kHalo);
         // partner images inside each shell: #{d in D_s : d == D_1[k] mod 2L}
         for (int s = 0; s < kMaxShells; ++s)
             for (int k = 0; k < kMaxZ1; ++k) R.mult[s][k] = 0;
@@ -270,11 +274,14 @@ int make_plan(const smcx_desc* d, Plan& P)
     P.rows = false;
     if (P.group == P.m && P.nbuf == 1 && !(d->flags & SMCX_FLAG_TILES)) {
         bool same_m = true;
+        // basis-planar rows in the window; pitches that are multiples of 256
+        // bytes keep lanes' partner reads in the banks of their own sites
         int ncx = 0, prow = 0;
         for (const Replica& R : P.reps) {
             for (int a = 0; a < 3; ++a) same_m &= R.M[a] == P.reps[0].M[a];
             ncx = std::max(ncx, (int)R.edges[0].size());
-            prow = std::max(prow, R.prow);
+            prow = std::max(prow, (R.prowp + 255) & ~255);
+            same_m &= R.cp == P.reps[0].cp;  // offset tables hold one column pitch
         }
         // score: busy lanes per block x waves per CU (12 make up for latency)
         // x a small penalty when a single workgroup per CU leaves its
@@ -301,7 +308,7 @@ int make_plan(const smcx_desc* d, Plan& P)
                         wz = std::max(wz, wzr);
                     }
                     const int winb = prow * wy * wz;
-                    if (!fits || 2LL * prow * wy + 2LL * prow + 2 * P.m + 4 > 32767) continue;
+                    if (!fits || 2LL * prow * wy + 2LL * prow + (P.m + 1) * (int64_t)P.reps[0].cp > 32767) continue;
                     const int lds = tables + ((winb + 15) & ~15);
                     if (lds > 160 * 1024) continue;
                     const int block = (lanes + 63) / 64 * 64;
@@ -372,6 +379,13 @@ int lds_offset(const Plan& P, int LP, int WY, int b, int vx, int vy, int vz)
     return nb.dz * LP * WY + nb.dy * LP + P.m * nb.dx + (nb.bt - b);
 }
 
+// Same in a window of basis-planar rows with column pitch cp.
+int lds_offset_planar(const Plan& P, int LP, int WY, int cp, int b, int vx, int vy, int vz)
+{
+    const Nb nb = nb_of(kGeom[P.lattice], b, vx, vy, vz);
+    return nb.dz * LP * WY + nb.dy * LP + nb.dx + (nb.bt - b) * cp;
+}
+
 }  // namespace
 
 struct smcx_lattice {
@@ -381,7 +395,7 @@ struct smcx_lattice {
     size_t ws_bytes;
     bool epi_set = false;
     std::vector<double> V;       // [S][K][K]
-    std::vector<double> Dhost;   // [K][K][S][K]
+    std::vector<double> Dhost;   // [S][K][K][K]: D[s][t][p][q]
     std::vector<int64_t> counts_host;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
@@ -484,12 +498,13 @@ int timed_launch(smcx_lattice* h, const void* kernel, dim3 grid, int block, size
     return SMCX_OK;
 }
 
-int pack_all(smcx_lattice* h, bool unpack, hipStream_t st)
+int pack_all(smcx_lattice* h, bool unpack, bool planar, hipStream_t st)
 {
     const Plan& P = h->P;
     for (int r = 0; r < P.R; ++r) {
         const int64_t ncell = P.reps[r].N / P.m;
-        SMCX_HIP(launch_pack(P.lattice, P.K, unpack, h->occ, h->ws, (const RepDev*)(h->ws + P.off_reps), r, ncell, st));
+        SMCX_HIP(launch_pack(P.lattice, P.K, unpack, planar, h->occ, h->ws, (const RepDev*)(h->ws + P.off_reps), r,
+                             ncell, st));
     }
     return SMCX_OK;
 }
@@ -568,6 +583,8 @@ int smcx_lattice_init(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_de
         for (int a = 0; a < 3; ++a) origins.insert(origins.end(), R.origin[a].begin(), R.origin[a].end());
         D.prow = R.prow;
         D.prows = R.prows;
+        D.cp = R.cp;
+        D.prowp = R.prowp;
         D.pad_off = R.pad_off;
         D.occ_off = R.occ_off;
         D.N = R.N;
@@ -588,7 +605,7 @@ int smcx_lattice_init(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_de
         for (int k = 0; k < P.Z1; ++k) {
             const int* d1 = G.v[0][k];
             offB[b * P.Z1 + k] = lds_offset(P, P.LP, P.WY, b, d1[0], d1[1], d1[2]);
-            if (P.rows) offB_r[b * P.Z1 + k] = lds_offset(P, P.rLP, P.rWY, b, d1[0], d1[1], d1[2]);
+            if (P.rows) offB_r[b * P.Z1 + k] = lds_offset_planar(P, P.rLP, P.rWY, P.reps[0].cp, b, d1[0], d1[1], d1[2]);
             const Nb nb = nb_of(G, b, d1[0], d1[1], d1[2]);
             int8_t* q = &pd[(b * P.Z1 + k) * 4];
             q[0] = (int8_t)nb.dx; q[1] = (int8_t)nb.dy; q[2] = (int8_t)nb.dz; q[3] = (int8_t)nb.bt;
@@ -597,7 +614,9 @@ int smcx_lattice_init(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_de
                 for (int n = 0; n < G.Z[s]; ++n, ++j) {
                     const int vx = d1[0] + G.v[s][n][0], vy = d1[1] + G.v[s][n][1], vz = d1[2] + G.v[s][n][2];
                     offP[(b * P.Z1 + k) * P.sumZ + j] = (int16_t)lds_offset(P, P.LP, P.WY, b, vx, vy, vz);
-                    if (P.rows) offP_r[(b * P.Z1 + k) * P.sumZ + j] = (int16_t)lds_offset(P, P.rLP, P.rWY, b, vx, vy, vz);
+                    if (P.rows)
+                        offP_r[(b * P.Z1 + k) * P.sumZ + j] =
+                            (int16_t)lds_offset_planar(P, P.rLP, P.rWY, P.reps[0].cp, b, vx, vy, vz);
                 }
         }
     std::vector<int64_t> row_off(P.R + 1, 0);
@@ -699,7 +718,7 @@ int smcx_set_epi(smcx_lattice* h, const double* V, void* stream)
         for (int q = 0; q < K; ++q)
             for (int s = 0; s < S; ++s)
                 for (int t = 0; t < K; ++t)
-                    h->Dhost[((p * K + q) * S + s) * K + t] = V[(s * K + q) * K + t] - V[(s * K + p) * K + t];
+                    h->Dhost[((s * K + t) * K + p) * K + q] = V[(s * K + q) * K + t] - V[(s * K + p) * K + t];
     hipStream_t st = (hipStream_t)stream;
     SMCX_HIP(hipMemcpyAsync(h->ws + P.off_D, h->Dhost.data(), sizeof(double) * h->Dhost.size(), hipMemcpyHostToDevice, st));
     SMCX_HIP(hipStreamSynchronize(st));
@@ -727,7 +746,8 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
     const Plan& P = h->P;
     if (mode == SMCX_MODE_AUTO)
         mode = (P.R > 1 || P.total_sites <= (1 << 16)) ? SMCX_MODE_PERSISTENT : SMCX_MODE_STREAM;
-    if (int rc = pack_all(h, false, st)) return rc;
+    const bool planar = mode == SMCX_MODE_STREAM && P.rows;  // the row kernel reads basis-planar rows
+    if (int rc = pack_all(h, false, planar, st)) return rc;
     SweepArgs a = base_args(h);
     a.seed = seed;
     a.stats = stats_dev;
@@ -795,7 +815,7 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
             }
         }
     }
-    return pack_all(h, true, st);
+    return pack_all(h, true, planar, st);
 }
 
 int smcx_sweep(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t first_sweep, const double* beta_dev,
@@ -960,11 +980,11 @@ int smcx_ladder_capture(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, const 
     a.tau_begin = 0;
     a.tau_end = P.max_nA;
     a.nb = P.group;
-    int rc = pack_all(h, false, st);
+    int rc = pack_all(h, false, false, st);
     hipError_t e = hipSuccess;
     if (rc == SMCX_OK) e = launch_sweep(h->k_persistent, dim3(P.R), P.block, P.lds.total, st, a);
     if (rc == SMCX_OK && e == hipSuccess) e = launch_advance_counter(sweep_counter_dev, (uint32_t)n_sweeps, st);
-    if (rc == SMCX_OK && e == hipSuccess) rc = pack_all(h, true, st);
+    if (rc == SMCX_OK && e == hipSuccess) rc = pack_all(h, true, false, st);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(st, &graph);
     if (rc != SMCX_OK) {

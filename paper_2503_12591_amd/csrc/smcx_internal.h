@@ -143,6 +143,8 @@ struct RepDev {
     int32_t prows;       // rows per padded plane (L1 + 2H)
     int32_t alias;       // some partner has images in another shell (an edge of 2)
     int32_t rg[2];       // row kernel: groups of rows along y and z
+    int32_t cp;          // basis-planar padded copy (row kernel): column pitch, bytes per basis site
+    int32_t prowp;       // basis-planar padded copy: row pitch (m * cp)
     int64_t pad_off;     // byte offset of the padded copy in the workspace
     int64_t occ_off;     // first site of this replica in the occupancy array
     int64_t N;           // sites
@@ -194,7 +196,7 @@ struct SweepArgs {
     const int16_t* offP;       // [m][Z1][sumZ] partner-neighbour offsets relative to the active site
     const int32_t* offB;       // [m][Z1] partner offset relative to the active site
     const int8_t* pdisp;       // [m][Z1][4] partner cell displacement and basis
-    const double* Dtab;        // [K][K][S][K]: V_s[q][t] - V_s[p][t]
+    const double* Dtab;        // [S][K][K][K]: D[s][t][p][q] = V_s[q][t] - V_s[p][t]
     uint8_t* ws;               // workspace base (padded copies)
     const double* beta;        // beta[js * beta_stride + r]
     int64_t* stats;            // [R][3]

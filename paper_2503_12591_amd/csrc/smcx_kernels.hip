@@ -84,15 +84,29 @@ template <> struct Enc<2> {
 // species from its stored form F * species (F = 8 or 6, species < 8)
 __device__ __forceinline__ int species_of(int v, int F) { return F == 8 ? v >> 3 : (v * 43) >> 8; }
 
+// Padded copies of a replica: rows of conventional cells with a 2-cell
+// periodic halo on every axis.  Interleaved rows hold the m basis sites of a
+// cell side by side (byte m * (x + H) + b); basis-planar rows hold one column
+// per basis site (byte b * cp + x + H), so that neighbouring link cells' sites
+// of one basis are 4 bytes apart and a wave's LDS reads of them fall into
+// distinct banks.
+template <bool PLANAR>
+__device__ __forceinline__ int row_byte(const RepDev& rep, int m, int x, int b)
+{
+    return PLANAR ? b * rep.cp + x + kHalo : m * (x + kHalo) + b;
+}
+
 // Write one species value to a site and to every periodic image of it that
 // lies inside the padded copy.
+template <bool PLANAR>
 __device__ __forceinline__ void store_site(uint8_t* pad, const RepDev& rep, int m, int x, int y, int z,
                                            int b, uint8_t v)
 {
+    const int prow = PLANAR ? rep.prowp : rep.prow;
     if (x >= kHalo && x < rep.L[0] - kHalo && y >= kHalo && y < rep.L[1] - kHalo && z >= kHalo &&
         z < rep.L[2] - kHalo) {
         // away from the faces a site has no other image
-        pad[((int64_t)(z + kHalo) * rep.prows + (y + kHalo)) * rep.prow + m * (x + kHalo) + b] = v;
+        pad[((int64_t)(z + kHalo) * rep.prows + (y + kHalo)) * prow + row_byte<PLANAR>(rep, m, x, b)] = v;
         return;
     }
     int xs[3], ys[3], zs[3];
@@ -108,8 +122,8 @@ __device__ __forceinline__ void store_site(uint8_t* pad, const RepDev& rep, int 
     if (z >= rep.L[2] - kHalo) zs[nz++] = z - rep.L[2];
     for (int iz = 0; iz < nz; ++iz)
         for (int iy = 0; iy < ny; ++iy) {
-            uint8_t* row = pad + ((int64_t)(zs[iz] + kHalo) * rep.prows + (ys[iy] + kHalo)) * rep.prow;
-            for (int ix = 0; ix < nx; ++ix) row[m * (xs[ix] + kHalo) + b] = v;
+            uint8_t* row = pad + ((int64_t)(zs[iz] + kHalo) * rep.prows + (ys[iy] + kHalo)) * prow;
+            for (int ix = 0; ix < nx; ++ix) row[row_byte<PLANAR>(rep, m, xs[ix], b)] = v;
         }
 }
 
@@ -130,12 +144,33 @@ __device__ __forceinline__ uint64_t shl1_add(uint32_t sh, uint64_t acc) { return
 // The reads are rebased at the most negative offset (a window's neighbours lie
 // within two conventional cells on every axis), so that every per-neighbour
 // offset is a non-negative constant that fits the LDS instruction's immediate.
-template <int LAT, int B, typename CT>
-__device__ __forceinline__ void count_uniform(const uint8_t* win, int base, int LP, int PL, int S,
+// Smallest cell offset on each axis and smallest basis index over the
+// neighbours (all shells) of a basis-b site.
+constexpr Nb min_components(const Geometry& G, int b)
+{
+    Nb r{0, 0, 0, b};
+    for (int s = 0; s < kMaxShells; ++s)
+        for (int n = 0; n < G.Z[s]; ++n) {
+            const Nb nb = nb_of(G, b, G.v[s][n][0], G.v[s][n][1], G.v[s][n][2]);
+            r.dx = nb.dx < r.dx ? nb.dx : r.dx;
+            r.dy = nb.dy < r.dy ? nb.dy : r.dy;
+            r.dz = nb.dz < r.dz ? nb.dz : r.dz;
+            r.bt = nb.bt < r.bt ? nb.bt : r.bt;
+        }
+    return r;
+}
+
+template <int LAT, int B, bool PLANAR, typename CT>
+__device__ __forceinline__ void count_uniform(const uint8_t* win, int base, int LP, int PL, int CP, int S,
                                               CT (&A)[kMaxShells])
 {
     constexpr Geometry G = kGeom[LAT];
-    const int lo = -kHalo * PL - kHalo * LP - G.m * kHalo - (G.m - 1);
+    // interleaved rows: x step m, basis step 1; basis-planar rows: x step 1, basis step CP
+    const int XS = PLANAR ? 1 : G.m, BS = PLANAR ? CP : 1;
+    // rebase at the smallest neighbour component on every axis (and basis):
+    // the window holds every neighbour, so base + lo stays inside it
+    constexpr Nb mn = min_components(G, B);
+    const int lo = mn.dz * PL + mn.dy * LP + XS * mn.dx + BS * (mn.bt - B);
     const uint8_t* w = win + (base + lo);
 #pragma unroll
     for (int s = 0; s < kMaxShells; ++s) {
@@ -144,7 +179,7 @@ __device__ __forceinline__ void count_uniform(const uint8_t* win, int base, int 
 #pragma unroll
             for (int n = 0; n < G.Z[s]; ++n) {
                 const Nb nb = nb_of(G, B, G.v[s][n][0], G.v[s][n][1], G.v[s][n][2]);
-                const int off = nb.dz * PL + nb.dy * LP + G.m * nb.dx + (nb.bt - B);
+                const int off = nb.dz * PL + nb.dy * LP + XS * nb.dx + BS * (nb.bt - B);
                 acc = shl1_add(w[off - lo], acc);
             }
         }
@@ -326,7 +361,10 @@ __device__ __forceinline__ void stage_async(const SweepArgs& A, const RepDev& re
     const int LPc = Geo::LP(A) >> 4;
     const int WY = Geo::WY(A);
     const int nslots = Geo::WZ(A) * WY * LPc;
-    const int gx1 = (m * (tg.w0[0] + tg.n[0] + kHalo) + 15) & ~15;
+    // row windows hold whole basis-planar rows; tile windows a byte range of
+    // interleaved rows
+    const int grow = Geo::rows ? rep.prowp : rep.prow;
+    const int gx1 = Geo::rows ? rep.prowp : (m * (tg.w0[0] + tg.n[0] + kHalo) + 15) & ~15;
     const int n16 = (gx1 - tg.gx0) >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -335,11 +373,11 @@ __device__ __forceinline__ void stage_async(const SweepArgs& A, const RepDev& re
     int R = j / LPc, col = j - R * LPc;
     int wz = R / WY, wy = R - wz * WY;
     const int dR = step / LPc, dcol = step - dR * LPc;
-    const uint8_t* base = pad + ((int64_t)(tg.w0[2] + kHalo) * rep.prows + (tg.w0[1] + kHalo)) * rep.prow + tg.gx0;
-    const int64_t plane = (int64_t)rep.prows * rep.prow;
+    const uint8_t* base = pad + ((int64_t)(tg.w0[2] + kHalo) * rep.prows + (tg.w0[1] + kHalo)) * grow + tg.gx0;
+    const int64_t plane = (int64_t)rep.prows * grow;
     for (int jb = wave * 64; jb < nslots; jb += step) {
         if (jb + lane < nslots && col < n16 && wy < tg.n[1] && wz < tg.n[2]) {
-            const uint8_t* src = base + wz * plane + (int64_t)wy * rep.prow + 16 * col;
+            const uint8_t* src = base + wz * plane + (int64_t)wy * grow + 16 * col;
             __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
                                              (__attribute__((address_space(3))) void*)(buf + 16 * jb), 16, 0, 0);
         }
@@ -424,7 +462,8 @@ __device__ __forceinline__ void trial_read(const SweepArgs& A, const RepDev& rep
     constexpr int Z1 = G.Z[0];
     const int LP = Geo::LP(A), WY = Geo::WY(A), PL = LP * WY;
     const int S = Geo::S(A);
-    const int la = ((az - tg.w0[2]) * WY + (ay - tg.w0[1])) * LP + (m * (ax + kHalo) + B - tg.gx0);
+    constexpr bool PLANAR = Geo::rows;
+    const int la = ((az - tg.w0[2]) * WY + (ay - tg.w0[1])) * LP + row_byte<PLANAR>(rep, m, ax, B) - tg.gx0;
     const int64_t ia = B + (int64_t)m * (ax + (int64_t)rep.L[0] * (ay + (int64_t)rep.L[1] * az));
     uint32_t w0, w1, w2, w3;
     philox4x32_10((uint32_t)ia, (uint32_t)((uint64_t)ia >> 32), t, (uint32_t)r, (uint32_t)A.seed,
@@ -448,10 +487,10 @@ __device__ __forceinline__ void trial_read(const SweepArgs& A, const RepDev& rep
     L.la = la;
     L.lb = la + offb;
     if (p8 == q8) return;
-    count_uniform<LAT, B, CT>(win, la, LP, PL, S, L.Ca);
+    count_uniform<LAT, B, PLANAR, CT>(win, la, LP, PL, rep.cp, S, L.Ca);
     if constexpr (LAT == SMCX_BCC) {
         // the partner of a BCC site always sits on the other sublattice
-        count_uniform<LAT, 1 - B, CT>(win, la + offb, LP, PL, S, L.Cb);
+        count_uniform<LAT, 1 - B, PLANAR, CT>(win, la + offb, LP, PL, rep.cp, S, L.Cb);
     } else {
         count_table<LAT, CT>(win, la, T.offP + (B * Z1 + k) * A.sumZ, S, L.Cb);
     }
@@ -473,7 +512,9 @@ __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& re
     const int p8 = L.p8, q8 = L.q8, k = L.k;
     // species were checked < K at init; the clamp keeps table reads in bounds regardless
     const int p = min(species_of(p8, EN::F), K - 1), q = min(species_of(q8, EN::F), K - 1);
-    const double* Dp = T.D + (size_t)((p * K + q) * S) * K;
+    // D[s][t][p][q]: the lanes' (p, q) entries of one term lie in one
+    // K*K*8-byte block, so their reads do not collide in LDS banks
+    const double* Dp = T.D + (p * K + q);
     double dE = 0.0;
 #pragma unroll
     for (int s = 0; s < kMaxShells; ++s) {
@@ -485,7 +526,7 @@ __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& re
             for (int tt = 0; tt < EN::KP; ++tt) {
                 if (tt < K) {
                     const int c = (int)((d >> (EN::F * tt)) & EN::mask) - EN::half;
-                    dE = dE + (double)c * Dp[s * K + tt];
+                    dE = dE + (double)c * Dp[(s * K + tt) * K * K];
                 }
             }
         }
@@ -523,13 +564,13 @@ __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& re
         bz += bz < 0 ? rep.L[2] : (bz >= rep.L[2] ? -rep.L[2] : 0);
         // the padded copy holds F * species, like the window; the window copy
         // serves the next basis site's trial of this lane
-        store_site(pad, rep, m, L.ax, L.ay, L.az, L.b, (uint8_t)q8);
-        store_site(pad, rep, m, bx, by, bz, bb, (uint8_t)p8);
+        store_site<Geo::rows>(pad, rep, m, L.ax, L.ay, L.az, L.b, (uint8_t)q8);
+        store_site<Geo::rows>(pad, rep, m, bx, by, bz, bb, (uint8_t)p8);
         win[L.la] = (uint8_t)q8;
         win[L.lb] = (uint8_t)p8;
         if constexpr (Geo::rows) {
             // row windows span x in [-H, L + H): sites within H of an x face appear twice
-            const int Lx = rep.L[0], sh = m * Lx;
+            const int Lx = rep.L[0], sh = Lx;  // basis-planar rows: x step 1
             if (L.ax < kHalo) win[L.la + sh] = (uint8_t)q8;
             if (L.ax >= Lx - kHalo) win[L.la - sh] = (uint8_t)q8;
             if (ubx < kHalo) win[L.lb + sh] = (uint8_t)p8;
@@ -983,7 +1024,7 @@ __global__ void k_advance_counter(uint32_t* counter, uint32_t n)
 }
 
 // Natural layout -> padded copy (all halo images).
-template <int M>
+template <int M, bool PLANAR>
 __global__ void k_pack(const uint8_t* occ, uint8_t* ws, const RepDev* reps, int r, int F)
 {
     const RepDev& rep = reps[r];
@@ -997,12 +1038,12 @@ __global__ void k_pack(const uint8_t* occ, uint8_t* ws, const RepDev* reps, int 
         const int y = (int)(cr % rep.L[1]);
         const int z = (int)(cr / rep.L[1]);
 #pragma unroll
-        for (int b = 0; b < M; ++b) store_site(pad, rep, M, x, y, z, b, (uint8_t)(o[M * c + b] * F));
+        for (int b = 0; b < M; ++b) store_site<PLANAR>(pad, rep, M, x, y, z, b, (uint8_t)(o[M * c + b] * F));
     }
 }
 
 // Padded copy interior -> natural layout.
-template <int M>
+template <int M, bool PLANAR>
 __global__ void k_unpack(uint8_t* occ, const uint8_t* ws, const RepDev* reps, int r, int F)
 {
     const RepDev& rep = reps[r];
@@ -1015,9 +1056,9 @@ __global__ void k_unpack(uint8_t* occ, const uint8_t* ws, const RepDev* reps, in
         const int64_t cr = c / rep.L[0];
         const int y = (int)(cr % rep.L[1]);
         const int z = (int)(cr / rep.L[1]);
-        const uint8_t* row = pad + ((int64_t)(z + kHalo) * rep.prows + (y + kHalo)) * rep.prow + M * (x + kHalo);
+        const uint8_t* row = pad + ((int64_t)(z + kHalo) * rep.prows + (y + kHalo)) * (PLANAR ? rep.prowp : rep.prow);
 #pragma unroll
-        for (int b = 0; b < M; ++b) o[M * c + b] = (uint8_t)species_of(row[b], F);
+        for (int b = 0; b < M; ++b) o[M * c + b] = (uint8_t)species_of(row[row_byte<PLANAR>(rep, M, x, b)], F);
     }
 }
 
@@ -1224,20 +1265,28 @@ hipError_t sweep_occupancy(const void* kernel, int block, size_t lds, int* block
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel, block, lds);
 }
 
-hipError_t launch_pack(int lattice, int K, bool unpack, uint8_t* occ, uint8_t* ws, const RepDev* reps, int r,
-                       int64_t ncell, hipStream_t st)
+hipError_t launch_pack(int lattice, int K, bool unpack, bool planar, uint8_t* occ, uint8_t* ws,
+                       const RepDev* reps, int r, int64_t ncell, hipStream_t st)
 {
     int64_t nb = (ncell + kBlock - 1) / kBlock;
     if (nb > 65536) nb = 65536;
     if (nb < 1) nb = 1;
     const dim3 g((unsigned)nb), b(kBlock);
     const int F = field_bits_of(K);
+    auto go = [&](auto mt, auto pt) {
+        constexpr int M = decltype(mt)::value;
+        constexpr bool PL = decltype(pt)::value;
+        if (unpack) hipLaunchKernelGGL((k_unpack<M, PL>), g, b, 0, st, occ, ws, reps, r, F);
+        else hipLaunchKernelGGL((k_pack<M, PL>), g, b, 0, st, occ, ws, reps, r, F);
+    };
+    using T2 = std::integral_constant<int, 2>;
+    using T4 = std::integral_constant<int, 4>;
+    using Y = std::true_type;
+    using N = std::false_type;
     if (lattice == SMCX_BCC) {
-        if (unpack) hipLaunchKernelGGL(k_unpack<2>, g, b, 0, st, occ, ws, reps, r, F);
-        else hipLaunchKernelGGL(k_pack<2>, g, b, 0, st, occ, ws, reps, r, F);
+        if (planar) go(T2{}, Y{}); else go(T2{}, N{});
     } else {
-        if (unpack) hipLaunchKernelGGL(k_unpack<4>, g, b, 0, st, occ, ws, reps, r, F);
-        else hipLaunchKernelGGL(k_pack<4>, g, b, 0, st, occ, ws, reps, r, F);
+        if (planar) go(T4{}, Y{}); else go(T4{}, N{});
     }
     return hipGetLastError();
 }

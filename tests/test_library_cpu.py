@@ -83,7 +83,9 @@ def test_workspace_size_accounts_for_padded_copy(smcx):
     d, keep = make_desc(smcx, dims=((800, 800, 800),))
     rc, n = ws_size(smcx, d)
     assert rc == 0
-    prow = (2 * 804 + 15) // 16 * 16
+    # rows of the padded copy: interleaved (16-byte aligned m * (L + 4)) or
+    # basis-planar (m columns of 16-byte aligned L + 4); the region fits either
+    prow = max((2 * 804 + 15) // 16 * 16, 2 * ((804 + 15) // 16 * 16))
     assert n >= prow * 804 * 804
     assert n < prow * 804 * 804 + (1 << 22)
 
