@@ -308,7 +308,10 @@ int make_plan(const smcx_desc* d, Plan& P)
                         wz = std::max(wz, wzr);
                     }
                     const int winb = prow * wy * wz;
-                    if (!fits || 2LL * prow * wy + 2LL * prow + (P.m + 1) * (int64_t)P.reps[0].cp > 32767) continue;
+                    // FCC partners count through a table of 16-bit window offsets
+                    if (!fits || (P.lattice == SMCX_FCC &&
+                                  2LL * prow * wy + 2LL * prow + (P.m + 1) * (int64_t)P.reps[0].cp > 32767))
+                        continue;
                     const int lds = tables + ((winb + 15) & ~15);
                     if (lds > 160 * 1024) continue;
                     const int block = (lanes + 63) / 64 * 64;

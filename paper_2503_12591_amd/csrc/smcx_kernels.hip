@@ -172,16 +172,21 @@ __device__ __forceinline__ void count_uniform(const uint8_t* win, int base, int 
     constexpr Nb mn = min_components(G, B);
     const int lo = mn.dz * PL + mn.dy * LP + XS * mn.dx + BS * (mn.bt - B);
     const uint8_t* w = win + (base + lo);
+    // all reads of a shell are issued before its counter chain starts, so
+    // their LDS latencies overlap
 #pragma unroll
     for (int s = 0; s < kMaxShells; ++s) {
         CT acc = 0;
         if (s < S) {
+            uint32_t v[kMaxZ];
 #pragma unroll
             for (int n = 0; n < G.Z[s]; ++n) {
                 const Nb nb = nb_of(G, B, G.v[s][n][0], G.v[s][n][1], G.v[s][n][2]);
                 const int off = nb.dz * PL + nb.dy * LP + XS * nb.dx + BS * (nb.bt - B);
-                acc = shl1_add(w[off - lo], acc);
+                v[n] = w[off - lo];
             }
+#pragma unroll
+            for (int n = 0; n < G.Z[s]; ++n) acc = shl1_add(v[n], acc);
         }
         A[s] = acc;
     }
