@@ -1179,6 +1179,105 @@ __global__ __launch_bounds__(kBlock) void k_pair_counts(const uint8_t* occ, int6
 }
 
 // ---------------------------------------------------------------------------
+// Pair counts of up to 4 species through LDS tiles: a block stages TX x TY x
+// 16 conventional cells plus a 2-cell periodic halo of one configuration;
+// lane (x, y) walks the 16 cells along z, forms the packed neighbour
+// histogram of each site per shell (one byte read and one shift-add per
+// neighbour, offsets fixed at compile time) and adds it to 16-bit fields of
+// the row of the site's species.  tiles_per_block keeps every field below
+// 2^16 between flushes.
+// ---------------------------------------------------------------------------
+template <int LAT, int TX>
+__global__ __launch_bounds__(kBlock) void k_pair_counts_tiled(const uint8_t* occ, int64_t N, int L0, int L1, int L2,
+                                                              int K, int S, int tiles_per_block, int64_t* counts)
+{
+    constexpr Geometry G = kGeom[LAT];
+    constexpr int m = G.m;
+    constexpr int TY = kBlock / TX, TZ = 16;
+    constexpr int WX = TX + 2 * kHalo, WY = TY + 2 * kHalo, WZ = TZ + 2 * kHalo;
+    constexpr int LP = WX * m, PL = LP * WY;
+    __shared__ __align__(16) uint8_t win[PL * WZ];
+    const uint8_t* o = occ + (int64_t)blockIdx.y * N;
+    const int ntx = (L0 + TX - 1) / TX, nty = (L1 + TY - 1) / TY, ntz = (L2 + TZ - 1) / TZ;
+    const int64_t ntiles = (int64_t)ntx * nty * ntz;
+    const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
+    const int64_t t1 = min(t0 + (int64_t)tiles_per_block, ntiles);
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    auto wrap = [](int v, int L) {
+        v += v < 0 ? L : 0;
+        v -= v >= L ? L : 0;
+        return v >= L ? v % L : v;  // only lattices narrower than a tile wrap twice
+    };
+    uint32_t acc[4][kMaxShells][2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int s = 0; s < kMaxShells; ++s) acc[k][s][0] = acc[k][s][1] = 0;
+    for (int64_t ti = t0; ti < t1; ++ti) {
+        const int tx = (int)(ti % ntx);
+        const int64_t tr = ti / ntx;
+        const int ty = (int)(tr % nty), tz = (int)(tr / nty);
+        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+        __syncthreads();  // every lane is done with the previous tile
+        for (int c = threadIdx.x; c < WX * WY * WZ; c += blockDim.x) {
+            const int wx = c % WX, wr = c / WX, wy = wr % WY, wz = wr / WY;
+            const int x = wrap(x0 + wx - kHalo, L0), y = wrap(y0 + wy - kHalo, L1), z = wrap(z0 + wz - kHalo, L2);
+            const int64_t cell = x + (int64_t)L0 * (y + (int64_t)L1 * z);
+            uint8_t* d = win + (wz * WY + wy) * LP + wx * m;
+            if constexpr (m == 2) *(uint16_t*)d = *(const uint16_t*)(o + 2 * cell);
+            else *(uint32_t*)d = *(const uint32_t*)(o + 4 * cell);
+        }
+        __syncthreads();
+        if (x0 + lx >= L0 || y0 + ly >= L1) continue;
+        for (int lz = 0; lz < TZ && z0 + lz < L2; ++lz) {
+#pragma unroll
+            for (int b = 0; b < m; ++b) {
+                const int base = ((lz + kHalo) * WY + (ly + kHalo)) * LP + (lx + kHalo) * m + b;
+                const int sig = win[base];
+#pragma unroll
+                for (int s = 0; s < kMaxShells; ++s) {
+                    if (s < S) {
+                        uint32_t v[kMaxZ];
+#pragma unroll
+                        for (int n = 0; n < G.Z[s]; ++n) {
+                            const Nb nb = nb_of(G, b, G.v[s][n][0], G.v[s][n][1], G.v[s][n][2]);
+                            v[n] = win[base + nb.dz * PL + nb.dy * LP + m * nb.dx + (nb.bt - b)];
+                        }
+                        uint32_t h = 0;
+#pragma unroll
+                        for (int n = 0; n < G.Z[s]; ++n) h += 1u << (8 * v[n]);
+                        // 8-bit fields (<= 24 each) -> two words of 16-bit fields
+                        const uint32_t lo = (h & 0xFFu) | ((h & 0xFF00u) << 8);
+                        const uint32_t hi = ((h >> 16) & 0xFFu) | ((h >> 8) & 0xFF0000u);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            acc[k][s][0] += sig == k ? lo : 0u;
+                            acc[k][s][1] += sig == k ? hi : 0u;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    int64_t* C = counts + (int64_t)blockIdx.y * S * K * K;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int s = 0; s < kMaxShells; ++s)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (k >= K || s >= S) continue;
+                const uint32_t a = wave_sum(acc[k][s][j] & 0xFFFFu);
+                const uint32_t bsum = wave_sum(acc[k][s][j] >> 16);
+                if ((threadIdx.x & 63) == 0) {
+                    if (2 * j < K && a) atomicAdd((unsigned long long*)&C[(s * K + k) * K + 2 * j], (unsigned long long)a);
+                    if (2 * j + 1 < K && bsum)
+                        atomicAdd((unsigned long long*)&C[(s * K + k) * K + 2 * j + 1], (unsigned long long)bsum);
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
@@ -1332,6 +1431,26 @@ hipError_t launch_advance_counter(uint32_t* counter, uint32_t n, hipStream_t st)
 hipError_t launch_pair_counts(int lattice, int K, int S, const uint8_t* occ, int64_t N, const int32_t* L,
                               int B, int64_t* counts, hipStream_t st)
 {
+    if (K <= 4) {
+        // lanes 64 x 4 cells (16 x 16 for narrow lattices), 16 cells deep;
+        // at most 2048 sites per lane between flushes keeps every 16-bit
+        // field exact (a site adds at most 24 to a field)
+        const int m = lattice == SMCX_BCC ? 2 : 4;
+        const bool wide = L[0] >= 48;
+        const int TX = wide ? 64 : 16, TY = kBlock / TX;
+        const int64_t ntiles = (int64_t)((L[0] + TX - 1) / TX) * ((L[1] + TY - 1) / TY) * ((L[2] + 15) / 16);
+        const int tpb = 2048 / (m * 16);
+        const int64_t nbx = (ntiles + tpb - 1) / tpb;
+        if (nbx > 0x7fffffff || B > 65535) return hipErrorInvalidValue;
+        const dim3 g((unsigned)nbx, (unsigned)B), b(kBlock);
+        auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g, b, 0, st, occ, N, L[0], L[1], L[2], K, S, tpb, counts); };
+        if (lattice == SMCX_BCC) {
+            if (wide) go(k_pair_counts_tiled<SMCX_BCC, 64>); else go(k_pair_counts_tiled<SMCX_BCC, 16>);
+        } else {
+            if (wide) go(k_pair_counts_tiled<SMCX_FCC, 64>); else go(k_pair_counts_tiled<SMCX_FCC, 16>);
+        }
+        return hipGetLastError();
+    }
     const int64_t ncell = (int64_t)L[0] * L[1] * L[2];
     // <= 2048 sites per lane between flushes keeps the 16-bit fields exact
     const int m = lattice == SMCX_BCC ? 2 : 4;
