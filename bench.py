@@ -26,6 +26,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# 32-bit VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+Z_SHELLS = {0: (8, 6, 12, 24), 1: (12, 6, 24, 12)}
+
+
+def algorithmic_ops_per_trial(lattice, K, S):
+    """32-bit ALU operations one trial needs in the counted-neighbour form:
+    Philox4x32-10 (10 rounds of two 32x32->64 products = 4 multiplies, and 4
+    xors) 80; partner index and uniform 4; one shift-add per neighbour of
+    either site 2*sum(Z); per (shell, species) term extract, convert, multiply
+    and add 4*S*K; decision 4."""
+    return 80 + 4 + 2 * sum(Z_SHELLS[lattice][:S]) + 4 * S * K + 4
 
 
 def parse():
@@ -173,6 +185,9 @@ def main():
     kernel = "k_rows" if abs(launches_per_sweep - M[1] * M[2]) < 1e-9 else "k_ministep"
     bytes_per_launch = algorithmic_bytes_per_launch(cells, N, 2, launches_per_sweep)
     achieved = bytes_per_launch / avg_launch_s / 1e9 if args.mode == "stream" else None
+    trials_per_launch = N * args.steps * spst / max(launches, 1)
+    ops = algorithmic_ops_per_trial(lattice, K, S)
+    alu_achieved = trials_per_launch * ops / avg_launch_s / 1e12
     traffic = None
     dtag = "x".join(str(d) for d in dims) if len(set(dims)) > 1 else str(dims[0])
     tfile = os.path.join(ROOT, "profiles", f"traffic_{kernel[2:]}_bcc{dtag}_ell{args.ell}.json")
@@ -201,11 +216,8 @@ def main():
                    "window_buffers": 2 if args.double_buffer else 1,
                    "accepted_frac": float(st1[1] - st0[1]) / attempted,
                    "near_ties": int(tie_count.item())},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": kernel,
-                     "avg_launch_us": avg_launch_s * 1e6, "launches": launches,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "roofline": roofline(kernel, achieved, alu_achieved, traffic, avg_launch_s, launches, bytes_per_launch,
+                             trials_per_launch, ops, value, nA),
         "wall_s": wall,
     }
     if not args.no_ladder:
@@ -217,6 +229,29 @@ def main():
                                            args.cpu_seconds)
     lat.close()
     print(json.dumps(out), flush=True)
+
+
+def roofline(kernel, hbm_gbs, alu_tops, traffic, avg_launch_s, launches, bytes_per_launch, trials_per_launch,
+             ops, swaps_per_s, n_ministeps):
+    """The sweep kernel's bound.  The tile kernel re-reads every link cell of
+    the lattice once per offset (HBM-bound); the row kernel reads it once per
+    (o_y, o_z) group and is limited by its ALU work, so it is priced against
+    the chip's 32-bit ALU lane-operation rate with the algorithmic operations
+    per trial; the HBM figures are kept beside it."""
+    hbm = {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": None if hbm_gbs is None else hbm_gbs / HBM_PEAK_GBS,
+           "algorithmic_bytes_per_launch": bytes_per_launch,
+           # bandwidth a one-launch-per-mini-step schedule (every byte re-read per
+           # mini-step, 2 bytes written per trial) would need for this throughput
+           "per_ministep_schedule_equivalent": swaps_per_s * (n_ministeps + 2.0) / 1e9}
+    common = {"kernel": kernel, "avg_launch_us": avg_launch_s * 1e6, "launches": launches, "traffic": traffic}
+    if kernel == "k_rows":
+        return {"bound": "alu", "achieved": alu_tops, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
+                "frac": alu_tops / ALU_PEAK_TOPS, "ops_per_trial": ops, "trials_per_launch": trials_per_launch,
+                **common, "hbm": hbm}
+    return {"bound": "hbm", "achieved": hbm["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm["frac"],
+            "algorithmic_bytes_per_launch": bytes_per_launch, **common,
+            "alu": {"achieved": alu_tops, "peak": ALU_PEAK_TOPS, "unit": "Tops/s", "ops_per_trial": ops}}
 
 
 def ladder_bench(args):
@@ -342,7 +377,7 @@ def _copy_factor(d, counter, nbytes=1 << 30):
 def summarize(args):
     kind, rest = args.summarize[0], args.summarize[1:]
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    tag = f"ministep_bcc{args.edge}_ell{args.ell}"
+    tag = f"bcc{args.edge}_ell{args.ell}"
     if kind == "trace":
         d, cmd = rest[0], " ".join(rest[1:])
         rows = _csv(d, "kernel_stats.csv")
@@ -357,18 +392,21 @@ def summarize(args):
             lines.append(f"{int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.1f} "
                          f"{float(r['MinNs']) / 1e3:10.1f} {float(r['MaxNs']) / 1e3:10.1f} "
                          f"{float(r['TotalDurationNs']) / 1e6:10.2f} {float(r['Percentage']):6.2f}  {name}")
-        with open(os.path.join(ROOT, "profiles", f"{tag}_kernel_trace.txt"), "w") as f:
+        with open(os.path.join(ROOT, "profiles", f"sweep_{tag}_kernel_trace.txt"), "w") as f:
             f.write("\n".join(lines) + "\n")
     elif kind == "traffic":
         fd, wd, cfd, cwd, cmd = rest[0], rest[1], rest[2], rest[3], " ".join(rest[4:])
-        is_k = lambda n: "k_ministep" in n
+        names = {r["Kernel_Name"] for r in _csv(fd, "counter_collection.csv")}
+        kname = "k_rows" if any("k_rows" in n for n in names) else "k_ministep"
+        tag = f"{kname[2:]}_bcc{args.edge}_ell{args.ell}"
+        is_k = lambda n: kname in n
         fk, nf = _per_dispatch(fd, "FETCH_SIZE", is_k)
         wk, nw = _per_dispatch(wd, "WRITE_SIZE", is_k)
         ff, fcopy = _copy_factor(cfd, "FETCH_SIZE")
         fw, wcopy = _copy_factor(cwd, "WRITE_SIZE")
         rd = fk * 1024 * ff
         wr = wk * 1024 * fw
-        lines = [f"# HBM traffic of k_ministep: BCC {args.edge}^3 benchmark, link cell {args.ell}",
+        lines = [f"# HBM traffic of {kname}: BCC {args.edge}^3 benchmark, link cell {args.ell}",
                  f"# command (one pass per counter): {cmd}",
                  "# calibration: bench.py --copy-probe (torch copy of 1 GiB) under the same counters", "",
                  f"FETCH_SIZE per dispatch (KiB, avg over {nf}): {fk:.1f}",
@@ -383,6 +421,35 @@ def summarize(args):
         with open(os.path.join(ROOT, "profiles", f"traffic_{tag}.json"), "w") as f:
             json.dump({"bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
                        "kernel_build": kernel_fingerprint(), "command": cmd}, f, indent=1)
+    elif kind == "counters":
+        # rest: counter-pass directories, then the command
+        dirs = [d for d in rest if os.path.isdir(d)]
+        cmd = " ".join(r for r in rest if r not in dirs)
+        vals, kname, ndisp = {}, None, 0
+        for d in dirs:
+            rows = _csv(d, "counter_collection.csv")
+            names = {r["Kernel_Name"] for r in rows}
+            kname = "k_rows" if any("k_rows" in n for n in names) else "k_ministep"
+            per = {}
+            for r in rows:
+                if kname in r["Kernel_Name"]:
+                    per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            for c, v in per.items():
+                vals[c] = sum(v) / len(v)
+                ndisp = len(v)
+        trials = args.edge ** 3 * 2  # one sweep of the benchmark lattice
+        lines = [f"# SQ counters of {kname}: BCC {args.edge}^3 benchmark, link cell {args.ell}",
+                 f"# command (one pass per group of counters): {cmd}",
+                 "# device totals per dispatch; 'per wave-trial' divides by the dispatch's trials / 64", "",
+                 f"{'counter':28s} {'per dispatch':>16s} {'per wave-trial':>15s}"]
+        for c in sorted(vals):
+            per_wt = vals[c] / (trials / ndisp / 64) if ndisp else float("nan")
+            lines.append(f"{c:28s} {vals[c]:16.1f} {per_wt:15.2f}")
+        if "SQ_LDS_BANK_CONFLICT" in vals and "SQ_LDS_IDX_ACTIVE" in vals:
+            lines.append(f"\nLDS bank-conflict cycles / LDS active cycles: "
+                         f"{vals['SQ_LDS_BANK_CONFLICT'] / vals['SQ_LDS_IDX_ACTIVE']:.3f}")
+        with open(os.path.join(ROOT, "profiles", f"{kname[2:]}_{tag}_sq_counters.txt"), "w") as f:
+            f.write("\n".join(lines) + "\n")
     else:
         raise SystemExit(f"unknown summary kind {kind}")
 
