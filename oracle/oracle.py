@@ -17,7 +17,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "smcx_oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+# SMCX_ORACLE_LIB points the tests at another build of this source (the
+# mutation tests use it to run the pins against planted mistakes)
+LIB = os.environ.get("SMCX_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 BCC, FCC = 0, 1
 MAXZ = 24
@@ -28,13 +30,21 @@ TRACE_DTYPE = np.dtype([("a", "<i8"), ("b", "<i8"), ("dE", "<f8"), ("k", "<i4"),
                         ("accepted", "<i4")])
 
 
+def compile_source(src: str, out: str) -> str:
+    """gcc, binary64, no contraction, OpenMP."""
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", out + ".tmp", src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (binary64, no contraction, OpenMP)."""
+    """Compile the oracle (no-op for an external build named by SMCX_ORACLE_LIB)."""
+    if os.environ.get("SMCX_ORACLE_LIB"):
+        return LIB
     if force or not os.path.exists(LIB):
-        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-               "-fPIC", "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(LIB + ".tmp", LIB)
+        compile_source(SRC, LIB)
     return LIB
 
 
