@@ -88,6 +88,7 @@ struct Plan {
     // row kernel (stream mode): lanes = RT[0] cells along x times RT[1] x RT[2] rows
     bool rows;
     int RT[3], rblock, rLP, rWY, rWZ;
+    int row_preset;  // compile-time row window matching the plan, or -1
     LdsLayout rlds;
     size_t off_rowoff, off_offP_r, off_offB_r;
     int64_t total_rowgroups;
@@ -272,6 +273,7 @@ int make_plan(const smcx_desc* d, Plan& P)
     // and windows no taller than the lattice on y and z (so no site appears
     // twice in a window except through the x halo).
     P.rows = false;
+    P.row_preset = -1;
     if (P.group == P.m && P.nbuf == 1 && !(d->flags & SMCX_FLAG_TILES)) {
         bool same_m = true;
         // basis-planar rows in the window; pitches that are multiples of 256
@@ -338,6 +340,13 @@ int make_plan(const smcx_desc* d, Plan& P)
             P.rWY = best[2];
             P.rWZ = best[3];
             P.rlds = lds_layout(P.lattice, P.K, P.S, P.Z1, P.sumZ, best_win, 1);
+            P.row_preset = -1;
+            for (int pi = 0; pi < kNumRowPresets; ++pi) {
+                const RowPreset& q = kRowPresets[pi];
+                if (q.lattice == P.lattice && q.K == P.K && q.S == P.S && q.cp == P.reps[0].cp && q.LP == P.rLP &&
+                    q.WY == P.rWY && q.WZ == P.rWZ && q.rt0 == P.RT[0] && q.rt1 == P.RT[1] && q.rt2 == P.RT[2])
+                    P.row_preset = pi;
+            }
             P.total_rowgroups = 0;
             for (Replica& R : P.reps) {
                 R.rg[0] = ((int)R.edges[1].size() + P.RT[1] - 1) / P.RT[1];
@@ -662,7 +671,7 @@ int smcx_lattice_init(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_de
     SMCX_HIP(sweep_occupancy(h->k_stream, P.block, P.lds.total, &per_cu));
     h->stream_wgs = 8 * std::max(1, (cus / 8) * std::max(1, per_cu));
     if (P.rows) {
-        h->k_rows = row_kernel(P.lattice, P.K, P.S, P.rblock);
+        h->k_rows = row_kernel(P.lattice, P.K, P.S, P.rblock, P.row_preset);
         SMCX_HIP(set_sweep_lds_limit(h->k_rows, P.rlds.total));
         int rcu = 1;
         SMCX_HIP(sweep_occupancy(h->k_rows, P.rblock, P.rlds.total, &rcu));

@@ -171,6 +171,17 @@ constexpr Preset kPresets[] = {
 };
 constexpr int kNumPresets = sizeof(kPresets) / sizeof(kPresets[0]);
 
+// Compile-time row windows (row kernel): column pitch, window row pitch and
+// depths, lanes (cells along x, rows along y and z) and species / shells.
+// With them every neighbour offset in the window is a constant.
+struct RowPreset {
+    int lattice, K, S, cp, LP, WY, WZ, rt0, rt1, rt2;
+};
+constexpr RowPreset kRowPresets[] = {
+    {SMCX_BCC, 4, 4, 816, 1792, 9, 9, 200, 2, 2},  // 800-cell rows, link cells of 4, 2 x 2 rows per workgroup
+};
+constexpr int kNumRowPresets = sizeof(kRowPresets) / sizeof(kRowPresets[0]);
+
 constexpr int preset_m(const Preset& p) { return p.lattice == SMCX_BCC ? 2 : 4; }
 constexpr int preset_w(int t, int ell) { return ell * (t - 1) + 1 + 2 * kHalo; }
 constexpr int preset_LP(const Preset& p)

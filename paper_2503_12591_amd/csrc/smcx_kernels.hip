@@ -265,6 +265,7 @@ struct GeoRt {
     __device__ static int block(const SweepArgs&) { return blockDim.x; }
     __device__ static int K(const SweepArgs& A) { return A.K; }
     __device__ static int S(const SweepArgs& A) { return A.S; }
+    __device__ static int CP(const RepDev& rep) { return rep.cp; }
 };
 
 template <int PI>
@@ -283,6 +284,7 @@ struct GeoFix {
     __device__ static constexpr int block(const SweepArgs&) { return (P.tx * P.ty * P.tz + 63) / 64 * 64; }
     __device__ static constexpr int K(const SweepArgs&) { return P.K; }
     __device__ static constexpr int S(const SweepArgs&) { return P.S; }
+    __device__ static int CP(const RepDev& rep) { return rep.cp; }  // tile windows are interleaved
 };
 
 // Row windows: the window holds whole padded x-rows (periodic images of the
@@ -294,6 +296,20 @@ struct GeoRow : GeoRt {
     static constexpr bool rows = true;
     __device__ static int K(const SweepArgs& A) { return KK ? KK : A.K; }
     __device__ static int S(const SweepArgs& A) { return SS ? SS : A.S; }
+};
+
+// Row windows of a compile-time preset.
+template <int PI>
+struct GeoRowFix : GeoRt {
+    static constexpr RowPreset P = kRowPresets[PI];
+    static constexpr bool rows = true;
+    __device__ static constexpr int T(const SweepArgs&, int a) { return a == 0 ? P.rt0 : (a == 1 ? P.rt1 : P.rt2); }
+    __device__ static constexpr int LP(const SweepArgs&) { return P.LP; }
+    __device__ static constexpr int WY(const SweepArgs&) { return P.WY; }
+    __device__ static constexpr int WZ(const SweepArgs&) { return P.WZ; }
+    __device__ static constexpr int K(const SweepArgs&) { return P.K; }
+    __device__ static constexpr int S(const SweepArgs&) { return P.S; }
+    __device__ static constexpr int CP(const RepDev&) { return P.cp; }
 };
 
 struct TileGeom {
@@ -468,7 +484,8 @@ __device__ __forceinline__ void trial_read(const SweepArgs& A, const RepDev& rep
     const int LP = Geo::LP(A), WY = Geo::WY(A), PL = LP * WY;
     const int S = Geo::S(A);
     constexpr bool PLANAR = Geo::rows;
-    const int la = ((az - tg.w0[2]) * WY + (ay - tg.w0[1])) * LP + row_byte<PLANAR>(rep, m, ax, B) - tg.gx0;
+    const int la = ((az - tg.w0[2]) * WY + (ay - tg.w0[1])) * LP +
+                   (PLANAR ? B * Geo::CP(rep) + ax + kHalo : m * (ax + kHalo) + B) - tg.gx0;
     const int64_t ia = B + (int64_t)m * (ax + (int64_t)rep.L[0] * (ay + (int64_t)rep.L[1] * az));
     uint32_t w0, w1, w2, w3;
     philox4x32_10((uint32_t)ia, (uint32_t)((uint64_t)ia >> 32), t, (uint32_t)r, (uint32_t)A.seed,
@@ -492,10 +509,10 @@ __device__ __forceinline__ void trial_read(const SweepArgs& A, const RepDev& rep
     L.la = la;
     L.lb = la + offb;
     if (p8 == q8) return;
-    count_uniform<LAT, B, PLANAR, CT>(win, la, LP, PL, rep.cp, S, L.Ca);
+    count_uniform<LAT, B, PLANAR, CT>(win, la, LP, PL, Geo::CP(rep), S, L.Ca);
     if constexpr (LAT == SMCX_BCC) {
         // the partner of a BCC site always sits on the other sublattice
-        count_uniform<LAT, 1 - B, PLANAR, CT>(win, la + offb, LP, PL, rep.cp, S, L.Cb);
+        count_uniform<LAT, 1 - B, PLANAR, CT>(win, la + offb, LP, PL, Geo::CP(rep), S, L.Cb);
     } else {
         count_table<LAT, CT>(win, la, T.offP + (B * Z1 + k) * A.sumZ, S, L.Cb);
     }
@@ -905,7 +922,8 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
     const int64_t lo = xcd * chunk;
     const int64_t hi = min(lo + chunk, total);
     const int l = threadIdx.x;
-    const int lx = l % A.T[0], ly = (l / A.T[0]) % A.T[1], lz = l / (A.T[0] * A.T[1]);
+    const int T0 = Geo::T(A, 0), T1 = Geo::T(A, 1), T2 = Geo::T(A, 2);
+    const int lx = l % T0, ly = (l / T0) % T1, lz = l / (T0 * T1);
     const uint32_t t = A.first_sweep;
     Stats st;
     int r_stats = -1;
@@ -927,10 +945,10 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
         TileGeom tg;
         tg.c0[0] = 0;
         tg.c1[0] = rep.nc[0];
-        tg.c0[1] = gy * A.T[1];
-        tg.c1[1] = min(tg.c0[1] + A.T[1], rep.nc[1]);
-        tg.c0[2] = gz * A.T[2];
-        tg.c1[2] = min(tg.c0[2] + A.T[2], rep.nc[2]);
+        tg.c0[1] = gy * T1;
+        tg.c1[1] = min(tg.c0[1] + T1, rep.nc[1]);
+        tg.c0[2] = gz * T2;
+        tg.c1[2] = min(tg.c0[2] + T2, rep.nc[2]);
         tg.w0[0] = -kHalo;
         tg.n[0] = rep.L[0] + 2 * kHalo;
         tg.gx0 = 0;
@@ -946,7 +964,7 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
         stage_async<LAT, Geo>(A, rep, tg, A.ws + rep.pad_off, win);
         // this lane's cell while the loads fly
         const int cx = lx, cy = tg.c0[1] + ly, cz = tg.c0[2] + lz;
-        const bool in = lz < A.T[2] && cx < tg.c1[0] && cy < tg.c1[1] && cz < tg.c1[2];
+        const bool in = lz < T2 && cx < tg.c1[0] && cy < tg.c1[1] && cz < tg.c1[2];
         int x0 = 0, ex = 0, y0 = 0, ey = 0, z0 = 0, ez = 0;
         if (in) {
             x0 = cell_origin<Geo>(A, rep, 0, cx);
@@ -1335,8 +1353,14 @@ static const void* row_kernel_b(int lattice, int K, int S)
                   : (e == 3 ? row_kernel_e<SMCX_FCC, 3, MAXB>(K, S) : row_kernel_e<SMCX_FCC, 2, MAXB>(K, S));
 }
 
-const void* row_kernel(int lattice, int K, int S, int block)
+const void* row_kernel(int lattice, int K, int S, int block, int preset)
 {
+    static_assert(kNumRowPresets == 1, "row presets resolved below");
+    if (preset == 0) {
+        constexpr RowPreset q = kRowPresets[0];
+        constexpr int B = (q.rt0 * q.rt1 * q.rt2 + 63) / 64 * 64;
+        return (const void*)k_rows<q.lattice, 1, GeoRowFix<0>, (B <= kBlock ? kBlock : kMaxRowBlock)>;
+    }
     return block <= kBlock ? row_kernel_b<kBlock>(lattice, K, S) : row_kernel_b<kMaxRowBlock>(lattice, K, S);
 }
 

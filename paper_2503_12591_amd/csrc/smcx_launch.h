@@ -9,7 +9,7 @@
 namespace smcx {
 
 const void* sweep_kernel(int lattice, int K, bool persistent, int preset, int nbuf);
-const void* row_kernel(int lattice, int K, int S, int block);
+const void* row_kernel(int lattice, int K, int S, int block, int preset);
 hipError_t launch_sweep(const void* kernel, dim3 grid, int block, size_t lds, hipStream_t st, const SweepArgs& a);
 hipError_t set_sweep_lds_limit(const void* kernel, size_t lds);
 hipError_t sweep_occupancy(const void* kernel, int block, size_t lds, int* blocks_per_cu);
