@@ -231,6 +231,20 @@ int smcx_ladder_capture(smcx_lattice *h, int32_t n_sweeps, uint64_t seed, const 
                         uint32_t *sweep_counter_dev, int64_t *stats_dev, smcx_tie *ties_dev,
                         int32_t tie_cap, int32_t *tie_count_dev, void *stream, void **graph_out);
 
+/*
+ * Any sweep mode as a replayable graph.  Captures, on `stream`, the launches
+ * of smcx_sweep(h, n_sweeps, seed, first, beta_dev, ...) in `mode`, where the
+ * first sweep index is read from *sweep_counter_dev (device uint32) when the
+ * graph runs and advanced by n_sweeps at its end, so every replay continues
+ * the chain.  beta_dev: device double [n_sweeps][R], read at every replay.
+ * The other arguments are as for smcx_sweep; *graph_out receives an
+ * executable graph for smcx_graph_launch.  `stream` must be a created stream;
+ * nothing runs during the capture; timing must be disabled.
+ */
+int smcx_sweep_capture(smcx_lattice *h, int32_t n_sweeps, uint64_t seed, const double *beta_dev,
+                       uint32_t *sweep_counter_dev, int64_t *stats_dev, smcx_tie *ties_dev, int32_t tie_cap,
+                       int32_t *tie_count_dev, int32_t mode, void *stream, void **graph_out);
+
 int smcx_graph_launch(void *graph, void *stream);
 
 int smcx_graph_destroy(void *graph);

@@ -753,8 +753,11 @@ static int check_sweep_args(smcx_lattice* h, const double* beta_dev, int64_t* st
 // tau_end) of each; beta_dev row js (R entries) belongs to sweep js.
 static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t first_sweep, int tau_begin,
                       int tau_end, const double* beta_dev, int64_t* stats_dev, smcx_tie* ties_dev, int32_t tie_cap,
-                      int32_t* tie_count_dev, int32_t mode, hipStream_t st)
+                      int32_t* tie_count_dev, int32_t mode, hipStream_t st, uint32_t* sweep_counter = nullptr)
 {
+    // with a device sweep counter (graph capture) the kernels read the sweep
+    // index from it and first_sweep counts from 0
+    if (sweep_counter) first_sweep = 0;
     const Plan& P = h->P;
     if (mode == SMCX_MODE_AUTO)
         mode = (P.R > 1 || P.total_sites <= (1 << 16)) ? SMCX_MODE_PERSISTENT : SMCX_MODE_STREAM;
@@ -769,6 +772,7 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
     a.n_sweeps = n_sweeps;
     a.tau_begin = tau_begin;
     a.tau_end = tau_end;
+    a.sweep_counter = sweep_counter;
     // one launch per group of mini-steps that share an offset (and a window)
     auto group_end = [&](int g, int end) { return std::min(end, (g / P.group + 1) * P.group); };
     if (mode == SMCX_MODE_PERSISTENT) {
@@ -785,6 +789,7 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
         ra.ties = a.ties;
         ra.tie_cap = a.tie_cap;
         ra.tie_count = a.tie_count;
+        ra.sweep_counter = sweep_counter;
         const int G = P.m * P.reps[0].M[0];
         const dim3 grid((unsigned)std::min<int64_t>(h->rows_wgs, 8 * ((P.total_rowgroups + 7) / 8)));
         for (int js = 0; js < n_sweeps; ++js) {
@@ -997,6 +1002,41 @@ int smcx_ladder_capture(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, const 
     if (rc == SMCX_OK) e = launch_sweep(h->k_persistent, dim3(P.R), P.block, P.lds.total, st, a);
     if (rc == SMCX_OK && e == hipSuccess) e = launch_advance_counter(sweep_counter_dev, (uint32_t)n_sweeps, st);
     if (rc == SMCX_OK && e == hipSuccess) rc = pack_all(h, true, false, st);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(st, &graph);
+    if (rc != SMCX_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        return fail(SMCX_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(SMCX_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    *graph_out = (void*)exec;
+    return SMCX_OK;
+}
+
+int smcx_sweep_capture(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, const double* beta_dev,
+                       uint32_t* sweep_counter_dev, int64_t* stats_dev, smcx_tie* ties_dev, int32_t tie_cap,
+                       int32_t* tie_count_dev, int32_t mode, void* stream, void** graph_out)
+{
+    if (!graph_out) return fail(SMCX_E_INVALID_ARG, "graph_out is NULL");
+    *graph_out = nullptr;
+    if (n_sweeps < 1) return fail(SMCX_E_INVALID_ARG, "n_sweeps must be >= 1");
+    if (int rc = check_sweep_args(h, beta_dev, stats_dev, ties_dev, tie_cap, tie_count_dev, mode)) return rc;
+    if (!sweep_counter_dev) return fail(SMCX_E_INVALID_ARG, "sweep_counter_dev is NULL");
+    if (h->timing) return fail(SMCX_E_INVALID_ARG, "disable timing before capturing a graph");
+    if (stream == nullptr) return fail(SMCX_E_INVALID_ARG, "the legacy default stream cannot be captured; pass a created stream");
+    hipStream_t st = (hipStream_t)stream;
+    SMCX_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int rc = run_sweeps(h, n_sweeps, seed, 0, 0, h->P.max_nA, beta_dev, stats_dev, ties_dev, tie_cap, tie_count_dev,
+                        mode, st, sweep_counter_dev);
+    hipError_t e = hipSuccess;
+    if (rc == SMCX_OK) e = launch_advance_counter(sweep_counter_dev, (uint32_t)n_sweeps, st);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(st, &graph);
     if (rc != SMCX_OK) {

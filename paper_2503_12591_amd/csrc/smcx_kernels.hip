@@ -889,7 +889,9 @@ __global__ __launch_bounds__(kBlock) void k_ministep(SweepArgs A)
     auto beta_of = [&](int r) { return ld_const(A.beta, r); };
     Stats st;
     int r_stats = -1;
-    run_tiles<LAT, E, Geo, NBUF>(A, lo + blockIdx.x / 8, hi, W, A.g, A.nb, A.first_sweep, T, smem + A.lds_win,
+    // a captured sweep reads its sweep index from the device counter
+    const uint32_t t = A.sweep_counter ? *A.sweep_counter + A.first_sweep : A.first_sweep;
+    run_tiles<LAT, E, Geo, NBUF>(A, lo + blockIdx.x / 8, hi, W, A.g, A.nb, t, T, smem + A.lds_win,
                            smem + A.lds_win + A.win_bytes, tile_of, beta_of, st, r_stats);
     flush_stats(A, r_stats, st);
 }
@@ -924,7 +926,7 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
     const int l = threadIdx.x;
     const int T0 = Geo::T(A, 0), T1 = Geo::T(A, 1), T2 = Geo::T(A, 2);
     const int lx = l % T0, ly = (l / T0) % T1, lz = l / (T0 * T1);
-    const uint32_t t = A.first_sweep;
+    const uint32_t t = A.sweep_counter ? *A.sweep_counter + A.first_sweep : A.first_sweep;
     Stats st;
     int r_stats = -1;
     for (int64_t i = lo + blockIdx.x / 8; i < hi; i += W) {

@@ -27,6 +27,7 @@ EXPORTS = [
     "smcx_lattice_init", "smcx_lattice_destroy", "smcx_get_schedule", "smcx_set_epi", "smcx_sweep",
     "smcx_sweep_partial",
     "smcx_pair_counts", "smcx_energy", "smcx_sro", "smcx_energy_backward", "smcx_ladder_capture",
+    "smcx_sweep_capture",
     "smcx_graph_launch", "smcx_graph_destroy", "smcx_timing_enable", "smcx_timing_read",
 ]
 
@@ -70,6 +71,7 @@ def lib():
     L.smcx_sro.argtypes = [p, p, p, p]
     L.smcx_energy_backward.argtypes = [i32, p, i32, i32, p, i32, p, p]
     L.smcx_ladder_capture.argtypes = [p, i32, u64, p, p, p, p, i32, p, p, C.POINTER(p)]
+    L.smcx_sweep_capture.argtypes = [p, i32, u64, p, p, p, p, i32, p, i32, p, C.POINTER(p)]
     L.smcx_graph_launch.argtypes = [p, p]
     L.smcx_graph_destroy.argtypes = [p]
     L.smcx_timing_enable.argtypes = [p, i32]
@@ -282,13 +284,20 @@ class Lattice:
 
 
 class LadderGraph:
-    """A captured persistent ladder launch (fixed beta per replica)."""
+    """n_sweeps sweeps of every replica captured in a replayable graph with
+    fixed betas per replica; every replay continues the chain (the sweep index
+    lives in a device counter).  mode "persistent" captures the one-launch
+    ladder (smcx_ladder_capture); other modes capture smcx_sweep's launches
+    (smcx_sweep_capture)."""
 
     def __init__(self, lat: Lattice, n_sweeps: int, seed: int, betas, first_sweep: int = 0,
-                 tie_cap: int = 4096):
+                 tie_cap: int = 4096, mode: str = "persistent"):
         torch = lat.torch
         self.lat = lat
-        self.beta = torch.from_numpy(np.ascontiguousarray(np.asarray(betas, np.float64))).cuda()
+        b = np.ascontiguousarray(np.asarray(betas, np.float64).reshape(-1))
+        if mode != "persistent":
+            b = np.ascontiguousarray(np.tile(b, (n_sweeps, 1)))
+        self.beta = torch.from_numpy(b).cuda()
         self.counter = torch.tensor([first_sweep], dtype=torch.int32, device="cuda")
         self.stats = torch.zeros(lat.R * 3, dtype=torch.int64, device="cuda")
         self.ties = torch.zeros(max(tie_cap, 1) * TIE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
@@ -298,10 +307,16 @@ class LadderGraph:
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
-            _check(lib().smcx_ladder_capture(lat.h, n_sweeps, C.c_uint64(seed), _ptr(self.beta),
-                                             _ptr(self.counter), _ptr(self.stats), _ptr(self.ties),
-                                             tie_cap, _ptr(self.tie_count), _stream(torch),
-                                             C.byref(g)))
+            if mode == "persistent":
+                _check(lib().smcx_ladder_capture(lat.h, n_sweeps, C.c_uint64(seed), _ptr(self.beta),
+                                                 _ptr(self.counter), _ptr(self.stats), _ptr(self.ties),
+                                                 tie_cap, _ptr(self.tie_count), _stream(torch),
+                                                 C.byref(g)))
+            else:
+                _check(lib().smcx_sweep_capture(lat.h, n_sweeps, C.c_uint64(seed), _ptr(self.beta),
+                                                _ptr(self.counter), _ptr(self.stats), _ptr(self.ties),
+                                                tie_cap, _ptr(self.tie_count), MODES[mode], _stream(torch),
+                                                C.byref(g)))
         torch.cuda.current_stream().wait_stream(side)
         self.g = g
         self.n_sweeps = n_sweeps

@@ -289,13 +289,14 @@ def test_ladder_replicas_match_oracle(smcx, mode):
     lat.close()
 
 
-def test_ladder_graph_replays_continue_the_chain(smcx):
+@pytest.mark.parametrize("mode", ["persistent", "stream", "plain"])
+def test_ladder_graph_replays_continue_the_chain(smcx, mode):
     import torch
     dims, K, S, occs, V, betas = ladder_inputs(5, 5, 9, seed=8)
-    say("ladder graph")
+    say(f"ladder graph {mode}")
     lat = smcx.Lattice(BCC, dims, K, S, np.concatenate(occs))
     lat.set_epi(V)
-    g = smcx.LadderGraph(lat, 2, 31, betas, first_sweep=0)
+    g = smcx.LadderGraph(lat, 2, 31, betas, first_sweep=0, mode=mode)
     for rep in range(3):
         g.launch()
         torch.cuda.synchronize()
@@ -309,6 +310,30 @@ def test_ladder_graph_replays_continue_the_chain(smcx):
         O.run(BCC, dims[r], K, S, cells, ref, V, 31, [betas[r]] * 6, replica=r)
         assert np.array_equal(gpu[off:off + len(ref)], ref), f"replica {r}"
         off += len(ref)
+    g.close()
+    lat.close()
+
+
+def test_row_kernel_graph_replays(smcx):
+    """Captured stream sweeps with whole-row windows continue the chain."""
+    import torch
+    dims, K, S = (16, 12, 20), 4, 4
+    occ = rand_occ(2 * 16 * 12 * 20, K, 77)
+    V = sym_V(S, K, 0.03, 5)
+    b = float(I.beta_of_T(900.0))
+    say("row kernel graph")
+    lat = smcx.Lattice(BCC, dims, K, S, occ, ell=4)
+    lat.set_epi(V)
+    g = smcx.LadderGraph(lat, 3, 19, [b], first_sweep=0, mode="stream")
+    for _ in range(2):
+        g.launch()
+        torch.cuda.synchronize()
+    gpu = lat.occupancy()
+    cells, _ = lat.schedule(0)
+    ref = occ.copy()
+    O.run(BCC, dims, K, S, cells, ref, V, 19, [b] * 6)
+    assert np.array_equal(gpu, ref)
+    assert int(g.stats.cpu().numpy()[0]) == 6 * len(occ)
     g.close()
     lat.close()
 
