@@ -286,7 +286,7 @@ def ladder_bench(args):
     lat = smcx.Lattice(I.BCC, dims, lad.K, lad.S, work, ell=4)
     lat.set_epi(lad.V)
     sweep_no = 0
-    for mode, ns in (("plain", 2), ("stream", n), ("persistent", n)):
+    for mode, ns in (("plain", 2), ("stream", n), ("persistent", n)):  # stream: row windows where they apply
         bt = np.tile(lad.betas, (ns, 1))
         lat.sweep(1, 0, lad.betas.reshape(1, -1), first_sweep=sweep_no, mode=mode)  # warm-up
         sweep_no += 1
@@ -303,7 +303,7 @@ def ladder_bench(args):
     lat.close()
     best = smcx.autotune(I.BCC, dims, lad.K, lad.S, occ_dev, lad.V, lad.betas, sweeps=2)
     work = occ_dev.clone()
-    lat = smcx.Lattice(I.BCC, dims, lad.K, lad.S, work, ell=best["ell"], tile=best["tile"])
+    lat = smcx.Lattice(I.BCC, dims, lad.K, lad.S, work, ell=best["ell"], tile=best["tile"], rows=best["rows"])
     lat.set_epi(lad.V)
     bt = np.tile(lad.betas, (n, 1))
     lat.sweep(1, 0, lad.betas.reshape(1, -1), mode=best["mode"])
@@ -313,7 +313,7 @@ def ladder_bench(args):
     batched = max(res["stream"], res["persistent"], res["graph"], res["stream_graph"], res["tuned"])
     return {"workload": "bcc_ladder256_L16to48_k4_s4", "sites": N, "sweeps": n,
             "unit": "attempted swaps/s", "swaps_per_s": res,
-            "tuned_config": {"tile": best["tile"], "mode": best["mode"], "ell": best["ell"]},
+            "tuned_config": {"tile": best["tile"], "mode": best["mode"], "ell": best["ell"], "rows": best["rows"]},
             "batched_over_plain": batched / res["plain"],
             "batched_over_plain_graph": batched / res["plain_graph"]}
 

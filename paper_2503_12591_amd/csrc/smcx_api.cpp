@@ -87,6 +87,7 @@ struct Plan {
     int group;  // mini-steps of consecutive basis sites sharing one staged window (m, or 1 if an edge < 4)
     // row kernel (stream mode): lanes = RT[0] cells along x times RT[1] x RT[2] rows
     bool rows;
+    bool rows_mixed;  // replicas differ in mini-step decomposition: row launches only for whole sweeps
     int RT[3], rblock, rLP, rWY, rWZ;
     int row_preset;  // compile-time row window matching the plan, or -1
     LdsLayout rlds;
@@ -273,9 +274,10 @@ int make_plan(const smcx_desc* d, Plan& P)
     // and windows no taller than the lattice on y and z (so no site appears
     // twice in a window except through the x halo).
     P.rows = false;
+    P.rows_mixed = false;
     P.row_preset = -1;
     if (P.group == P.m && P.nbuf == 1 && !(d->flags & SMCX_FLAG_TILES)) {
-        bool same_m = true;
+        bool same_m = true, same_cp = true;
         // basis-planar rows in the window; pitches that are multiples of 256
         // bytes keep lanes' partner reads in the banks of their own sites
         int ncx = 0, prow = 0;
@@ -283,7 +285,7 @@ int make_plan(const smcx_desc* d, Plan& P)
             for (int a = 0; a < 3; ++a) same_m &= R.M[a] == P.reps[0].M[a];
             ncx = std::max(ncx, (int)R.edges[0].size());
             prow = std::max(prow, (R.prowp + 255) & ~255);
-            same_m &= R.cp == P.reps[0].cp;  // offset tables hold one column pitch
+            same_cp &= R.cp == P.reps[0].cp;
         }
         // score: busy lanes per block x waves per CU (12 make up for latency)
         // x a small penalty when a single workgroup per CU leaves its
@@ -291,7 +293,10 @@ int make_plan(const smcx_desc* d, Plan& P)
         const int tables = lds_layout(P.lattice, P.K, P.S, P.Z1, P.sumZ, 0, 1).total;
         double best_score = 0.0;
         int best_lanes = 0, best_win = 0, best[4] = {0, 0, 0, 0};
-        if (same_m && ncx <= kMaxRowBlock)
+        // FCC partners count through a table of window offsets, which holds one
+        // column pitch; BCC partners derive theirs per replica
+        P.rows_mixed = !same_m;
+        if ((same_cp || P.lattice == SMCX_BCC) && ncx <= kMaxRowBlock)
             for (int ry : {1, 2, 4, 8, 16})
                 for (int rz : {1, 2, 4, 8, 16}) {
                     const int lanes = ncx * ry * rz;
@@ -343,7 +348,7 @@ int make_plan(const smcx_desc* d, Plan& P)
             P.row_preset = -1;
             for (int pi = 0; pi < kNumRowPresets; ++pi) {
                 const RowPreset& q = kRowPresets[pi];
-                if (q.lattice == P.lattice && q.K == P.K && q.S == P.S && q.cp == P.reps[0].cp && q.LP == P.rLP &&
+                if (same_cp && q.lattice == P.lattice && q.K == P.K && q.S == P.S && q.cp == P.reps[0].cp && q.LP == P.rLP &&
                     q.WY == P.rWY && q.WZ == P.rWZ && q.rt0 == P.RT[0] && q.rt1 == P.RT[1] && q.rt2 == P.RT[2])
                     P.row_preset = pi;
             }
@@ -452,6 +457,7 @@ SweepArgs base_args(smcx_lattice* h)
     a.nbuf = P.nbuf;
     a.only_rep = -1;
     a.nb = 1;
+    a.gq = -1;
     a.sweep_counter = nullptr;
     return a;
 }
@@ -761,7 +767,10 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
     const Plan& P = h->P;
     if (mode == SMCX_MODE_AUTO)
         mode = (P.R > 1 || P.total_sites <= (1 << 16)) ? SMCX_MODE_PERSISTENT : SMCX_MODE_STREAM;
-    const bool planar = mode == SMCX_MODE_STREAM && P.rows;  // the row kernel reads basis-planar rows
+    // the row kernel reads basis-planar rows; replicas of different
+    // decompositions share its launches only over whole sweeps
+    const bool rows = mode == SMCX_MODE_STREAM && P.rows && (!P.rows_mixed || (tau_begin == 0 && tau_end >= P.max_nA));
+    const bool planar = rows;
     if (int rc = pack_all(h, false, planar, st)) return rc;
     SweepArgs a = base_args(h);
     a.seed = seed;
@@ -781,7 +790,7 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
         a.beta_stride = P.R;
         a.nb = P.group;
         if (int rc = timed_launch(h, h->k_persistent, dim3(P.R), P.block, P.lds.total, st, a)) return rc;
-    } else if (mode == SMCX_MODE_STREAM && P.rows) {
+    } else if (rows) {
         // one launch per (o_y, o_z) group: every o_x and basis site
         SweepArgs ra = row_args(h);
         ra.seed = a.seed;
@@ -792,9 +801,18 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
         ra.sweep_counter = sweep_counter;
         const int G = P.m * P.reps[0].M[0];
         const dim3 grid((unsigned)std::min<int64_t>(h->rows_wgs, 8 * ((P.total_rowgroups + 7) / 8)));
+        int max_groups = 0;
+        for (const Replica& R : P.reps) max_groups = std::max(max_groups, R.M[1] * R.M[2]);
         for (int js = 0; js < n_sweeps; ++js) {
             ra.first_sweep = first_sweep + (uint32_t)js;
             ra.beta = beta_dev + (int64_t)js * P.R;
+            if (P.rows_mixed) {
+                for (int q = 0; q < max_groups; ++q) {
+                    ra.gq = q;
+                    if (int rc = timed_launch(h, h->k_rows, grid, P.rblock, P.rlds.total, st, ra)) return rc;
+                }
+                continue;
+            }
             const int end = std::min(tau_end, P.max_nA);
             for (int g = tau_begin; g < end;) {
                 const int ge = std::min(end, (g / G + 1) * G);

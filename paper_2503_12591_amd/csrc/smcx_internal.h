@@ -226,6 +226,8 @@ struct SweepArgs {
     int32_t win_bytes;         // one window buffer
     int32_t nbuf;              // window buffers: 2 = next tile streams in during the trials, 1 = staged in turn
     int32_t g;                 // mini-step (stream / plain launches)
+    int32_t gq;                // row launches over replicas of different decompositions: group index q
+                               // (every replica runs its q-th (o_y, o_z) group, all offsets), else -1
     int32_t nb;                // stream / plain: mini-steps g .. g + nb - 1 (one offset o, consecutive basis
                                // sites) share one staged window; persistent: the group size (1 or m)
     int32_t tau_begin, tau_end; // persistent launches: mini-step range of every sweep

@@ -257,6 +257,7 @@ __device__ void load_tables(const SweepArgs& A, uint8_t* smem)
 struct GeoRt {
     static constexpr bool fixed = false;
     static constexpr bool rows = false;
+    static constexpr bool own_cp = false;
     static constexpr int ELL = 0;
     __device__ static int T(const SweepArgs& A, int a) { return A.T[a]; }
     __device__ static int LP(const SweepArgs& A) { return A.LP; }
@@ -274,6 +275,7 @@ struct GeoFix {
     static_assert(preset_ok(P), "tile start must be 16-byte aligned");
     static constexpr bool fixed = true;
     static constexpr bool rows = false;
+    static constexpr bool own_cp = false;
     static constexpr int ELL = P.ell;
     static constexpr int kLP = preset_LP(P), kWY = preset_WY(P), kWZ = preset_WZ(P);
     static constexpr int kBLOCK = (P.tx * P.ty * P.tz + 63) / 64 * 64;
@@ -294,6 +296,7 @@ struct GeoFix {
 template <int KK, int SS>
 struct GeoRow : GeoRt {
     static constexpr bool rows = true;
+    static constexpr bool own_cp = true;  // replicas may differ in column pitch
     __device__ static int K(const SweepArgs& A) { return KK ? KK : A.K; }
     __device__ static int S(const SweepArgs& A) { return SS ? SS : A.S; }
 };
@@ -493,7 +496,15 @@ __device__ __forceinline__ void trial_read(const SweepArgs& A, const RepDev& rep
     (void)w3;
     const int k = (int)__umulhi(w0, (uint32_t)Z1);
     const int p8 = win[la];
-    const int offb = T.offB[B * Z1 + k];
+    int offb;
+    if constexpr (Geo::own_cp && LAT == SMCX_BCC) {
+        // the partner's window offset from its cell displacement and this
+        // replica's column pitch (row windows of replicas of different widths)
+        const int8_t* q = T.pd + (B * Z1 + k) * 4;
+        offb = q[2] * PL + q[1] * LP + q[0] + (q[3] - B) * Geo::CP(rep);
+    } else {
+        offb = T.offB[B * Z1 + k];
+    }
     const int q8 = win[la + offb];
     L.active = 1;
     L.p8 = p8;
@@ -939,8 +950,15 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
         int64_t grp = i - ld_const(A.tile_off, a);
         uniform(r, grp);
         const RepDev& rep = rep_of(A, r);
-        if (A.g >= rep.nA) continue;
-        const int b0 = A.g % m, rest = A.g / m;
+        int g0 = A.g, gn = A.nb;
+        if (A.gq >= 0) {
+            // this replica's q-th (o_y, o_z) group, every offset o_x and basis site
+            if (A.gq >= rep.M[1] * rep.M[2]) continue;
+            gn = m * rep.M[0];
+            g0 = A.gq * gn;
+        }
+        if (g0 >= rep.nA) continue;
+        const int b0 = g0 % m, rest = g0 / m;
         const int ox0 = rest % rep.M[0];
         const int oy = (rest / rep.M[0]) % rep.M[1], oz = rest / (rep.M[0] * rep.M[1]);
         const int gy = (int)(grp % rep.rg[0]), gz = (int)(grp / rep.rg[0]);
@@ -984,8 +1002,8 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
             flush_stats(A, r_stats, st);
             r_stats = r;
         }
-        int tau = A.g, b = b0, ox = ox0;
-        const int tau1 = A.g + A.nb;
+        int tau = g0, b = b0, ox = ox0;
+        const int tau1 = g0 + gn;
         while (true) {
             const int nbb = min(m - b, tau1 - tau);
             if (yz && ox < ex) {

@@ -385,10 +385,12 @@ def EnergyFn():
 
 
 def autotune(lattice: int, dims, K: int, S: int, occ, V, betas, seed: int = 0, tiles=None,
-             modes=("persistent", "stream"), ells=(None,), sweeps: int = 2, cache: str | None = None):
+             modes=("persistent", "stream"), ells=(None,), rows=(True, False), sweeps: int = 2,
+             cache: str | None = None):
     """Choose the launch configuration with the most attempted swaps/s.
 
-    Every candidate (tile, mode, link-cell edge) runs `sweeps` sweeps (after
+    Every candidate (tile, mode, row windows or not, link-cell edge) runs
+    `sweeps` sweeps (after
     one untimed sweep) on a fresh copy of `occ` (host uint8 array or CUDA
     tensor, all replicas back to back) with inverse temperatures `betas` ([R]
     or scalar).  Tile and mode leave the trajectory unchanged; a link-cell
@@ -404,7 +406,7 @@ def autotune(lattice: int, dims, K: int, S: int, occ, V, betas, seed: int = 0, t
     if tiles is None:
         tiles = [(16, 4, 2), (16, 4, 4), (8, 4, 4), (8, 8, 2), (4, 4, 4)]
     key_src = json.dumps([lattice, dims.tolist(), K, S, [list(t) for t in tiles], list(modes),
-                          [e if e is None else int(e) for e in ells], sweeps])
+                          [e if e is None else int(e) for e in ells], [bool(x) for x in rows], sweeps])
     key = hashlib.sha256(key_src.encode()).hexdigest()[:16]
     if cache and os.path.exists(cache):
         with open(cache) as f:
@@ -419,29 +421,29 @@ def autotune(lattice: int, dims, K: int, S: int, occ, V, betas, seed: int = 0, t
     N = int((dims.prod(axis=1) * (2 if lattice == BCC else 4)).sum())
     b1 = np.broadcast_to(np.asarray(betas, np.float64).reshape(-1), (R,))
     table = []
-    for ell in ells:
-        for tile in tiles:
-            for mode in modes:
-                work = occ0.clone()
-                try:
-                    lat = Lattice(lattice, dims, K, S, work, ell=ell, tile=tile)
-                except SmcxError as e:
-                    table.append({"tile": list(tile), "mode": mode, "ell": ell, "error": str(e)})
-                    continue
-                lat.set_epi(V)
-                bt = np.tile(b1, (sweeps, 1))
-                lat.sweep(1, seed, b1.reshape(1, R), first_sweep=0, mode=mode)
-                torch.cuda.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                lat.sweep(sweeps, seed, bt, first_sweep=1, mode=mode)
-                e1.record()
-                torch.cuda.synchronize()
-                secs = e0.elapsed_time(e1) / 1e3
-                table.append({"tile": list(tile), "mode": mode, "ell": ell,
-                              "swaps_per_s": sweeps * N / secs})
-                lat.close()
-                del work
+    cands = [(ell, tile, mode, rw) for ell in ells for tile in tiles for mode in modes for rw in rows
+             if rw or mode == "stream"]  # row windows only change stream mode
+    for ell, tile, mode, rw in cands:
+        work = occ0.clone()
+        try:
+            lat = Lattice(lattice, dims, K, S, work, ell=ell, tile=tile, rows=rw)
+        except SmcxError as e:
+            table.append({"tile": list(tile), "mode": mode, "ell": ell, "rows": rw, "error": str(e)})
+            continue
+        lat.set_epi(V)
+        bt = np.tile(b1, (sweeps, 1))
+        lat.sweep(1, seed, b1.reshape(1, R), first_sweep=0, mode=mode)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lat.sweep(sweeps, seed, bt, first_sweep=1, mode=mode)
+        e1.record()
+        torch.cuda.synchronize()
+        secs = e0.elapsed_time(e1) / 1e3
+        table.append({"tile": list(tile), "mode": mode, "ell": ell, "rows": rw,
+                      "swaps_per_s": sweeps * N / secs})
+        lat.close()
+        del work
     ok = [t for t in table if "swaps_per_s" in t]
     if not ok:
         raise SmcxError("no candidate configuration could be built")

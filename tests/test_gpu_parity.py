@@ -186,11 +186,15 @@ def test_stream_rows_partial_ranges(smcx):
     parts.close()
 
 
-def test_stream_rows_multi_replica(smcx):
-    """Replicas of different shapes with the same mini-step decomposition run
-    in one row launch per group."""
+@pytest.mark.parametrize("dims", [
+    [[16, 16, 16], [20, 16, 12], [12, 24, 16]],   # one decomposition: launches per (o_y, o_z) group
+    [[16, 17, 16], [21, 18, 19], [13, 22, 20]],   # cells of 4 and 5: launches per group index
+], ids=["same", "mixed"])
+def test_stream_rows_multi_replica(smcx, dims):
+    """Replicas of different shapes in one row launch per group (of the same
+    mini-steps, or of each replica's q-th (o_y, o_z) group)."""
     from paper_2503_12591_amd import smcx as S
-    dims = np.array([[16, 16, 16], [20, 16, 12], [12, 24, 16]], np.int32)
+    dims = np.array(dims, np.int32)
     K, Sh = 4, 4
     occs = [rand_occ(int(2 * np.prod(d)), K, 50 + r) for r, d in enumerate(dims)]
     V = sym_V(Sh, K, 0.03, 21)
