@@ -278,27 +278,31 @@ int make_plan(const smcx_desc* d, Plan& P)
     P.row_preset = -1;
     if (P.group == P.m && P.nbuf == 1 && !(d->flags & SMCX_FLAG_TILES)) {
         bool same_m = true, same_cp = true;
-        // basis-planar rows in the window; pitches that are multiples of 256
-        // bytes keep lanes' partner reads in the banks of their own sites
-        int ncx = 0, prow = 0;
+        // basis-planar rows in the window; a pitch that is a multiple of 256
+        // bytes keeps lanes' partner reads in the banks of their own sites, a
+        // multiple of 128 costs a few two-way conflicts but may let one more
+        // workgroup fit per CU
+        int ncx = 0, prowp = 0;
         for (const Replica& R : P.reps) {
             for (int a = 0; a < 3; ++a) same_m &= R.M[a] == P.reps[0].M[a];
             ncx = std::max(ncx, (int)R.edges[0].size());
-            prow = std::max(prow, (R.prowp + 255) & ~255);
+            prowp = std::max(prowp, R.prowp);
             same_cp &= R.cp == P.reps[0].cp;
         }
         // score: busy lanes per block x waves per CU (12 make up for latency)
-        // x a small penalty when a single workgroup per CU leaves its
-        // staging exposed
+        // x a penalty when a single workgroup per CU leaves its staging
+        // exposed x a small one for the 128-byte pitch
         const int tables = lds_layout(P.lattice, P.K, P.S, P.Z1, P.sumZ, 0, 1).total;
         double best_score = 0.0;
-        int best_lanes = 0, best_win = 0, best[4] = {0, 0, 0, 0};
+        int best_lanes = 0, best_win = 0, best_prow = 0, best[4] = {0, 0, 0, 0};
         // FCC partners count through a table of window offsets, which holds one
         // column pitch; BCC partners derive theirs per replica
         P.rows_mixed = !same_m;
         if ((same_cp || P.lattice == SMCX_BCC) && ncx <= kMaxRowBlock)
+          for (int align : {256, 128})
             for (int ry : {1, 2, 4, 8, 16})
                 for (int rz : {1, 2, 4, 8, 16}) {
+                    const int prow = (prowp + align - 1) & ~(align - 1);
                     const int lanes = ncx * ry * rz;
                     if (lanes > kMaxRowBlock) continue;
                     int wy = 0, wz = 0;
@@ -327,11 +331,12 @@ int make_plan(const smcx_desc* d, Plan& P)
                     const int wgs = std::min(160 * 1024 / lds, wave_cap / waves);
                     if (wgs < 1) continue;
                     const double score = (double)lanes / block * std::min(1.0, wgs * waves / 12.0) *
-                                         (wgs == 1 ? 0.92 : 1.0);
+                                         (wgs == 1 ? 0.88 : 1.0) * (prow % 256 ? 0.98 : 1.0);
                     if (score > best_score + 1e-12 || (std::fabs(score - best_score) <= 1e-12 && winb < best_win)) {
                         best_score = score;
                         best_lanes = lanes;
                         best_win = winb;
+                        best_prow = prow;
                         best[0] = ry; best[1] = rz; best[2] = wy; best[3] = wz;
                     }
                 }
@@ -341,7 +346,7 @@ int make_plan(const smcx_desc* d, Plan& P)
             P.RT[1] = best[0];
             P.RT[2] = best[1];
             P.rblock = (best_lanes + 63) / 64 * 64;
-            P.rLP = prow;
+            P.rLP = best_prow;
             P.rWY = best[2];
             P.rWZ = best[3];
             P.rlds = lds_layout(P.lattice, P.K, P.S, P.Z1, P.sumZ, best_win, 1);

@@ -178,7 +178,7 @@ struct RowPreset {
     int lattice, K, S, cp, LP, WY, WZ, rt0, rt1, rt2;
 };
 constexpr RowPreset kRowPresets[] = {
-    {SMCX_BCC, 4, 4, 816, 1792, 9, 9, 200, 2, 2},  // 800-cell rows, link cells of 4, 2 x 2 rows per workgroup
+    {SMCX_BCC, 4, 4, 816, 1664, 5, 9, 200, 1, 2},  // 800-cell rows, link cells of 4, 1 x 2 rows per workgroup
 };
 constexpr int kNumRowPresets = sizeof(kRowPresets) / sizeof(kRowPresets[0]);
 
