@@ -160,6 +160,21 @@ constexpr Nb min_components(const Geometry& G, int b)
     return r;
 }
 
+// Smallest (lo) and largest (hi) cell displacement, over the y and z axes
+// and every basis site, of a site's nearest neighbours: the rows a swap
+// partner can lie in, relative to the active site's row.
+constexpr int partner_reach(const Geometry& G, bool hi)
+{
+    int r = 0;
+    for (int b = 0; b < G.m; ++b)
+        for (int n = 0; n < G.Z[0]; ++n) {
+            const Nb nb = nb_of(G, b, G.v[0][n][0], G.v[0][n][1], G.v[0][n][2]);
+            const int a = hi ? (nb.dy > nb.dz ? nb.dy : nb.dz) : (nb.dy < nb.dz ? nb.dy : nb.dz);
+            r = hi ? (a > r ? a : r) : (a < r ? a : r);
+        }
+    return r;
+}
+
 template <int LAT, int B, bool PLANAR, typename CT>
 __device__ __forceinline__ void count_uniform(const uint8_t* win, int base, int LP, int PL, int CP, int S,
                                               CT (&A)[kMaxShells])
@@ -171,7 +186,12 @@ __device__ __forceinline__ void count_uniform(const uint8_t* win, int base, int 
     // the window holds every neighbour, so base + lo stays inside it
     constexpr Nb mn = min_components(G, B);
     const int lo = mn.dz * PL + mn.dy * LP + XS * mn.dx + BS * (mn.bt - B);
-    const uint8_t* w = win + (base + lo);
+    // opaque to the compiler, so it keeps this base and every read's offset
+    // (non-negative, below 64 KiB) goes into the instruction's offset field
+    // instead of a per-read address add
+    int rb = base + lo;
+    asm("" : "+v"(rb));
+    const uint8_t* w = win + rb;
     // all reads of a shell are issued before its counter chain starts, so
     // their LDS latencies overlap
 #pragma unroll
@@ -597,8 +617,11 @@ __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& re
         bz += bz < 0 ? rep.L[2] : (bz >= rep.L[2] ? -rep.L[2] : 0);
         // the padded copy holds F * species, like the window; the window copy
         // serves the next basis site's trial of this lane
-        store_site<Geo::rows>(pad, rep, m, L.ax, L.ay, L.az, L.b, (uint8_t)q8);
-        store_site<Geo::rows>(pad, rep, m, bx, by, bz, bb, (uint8_t)p8);
+        // (row windows reach HBM in one copy of their changed rows per group)
+        if constexpr (!Geo::rows) {
+            store_site<false>(pad, rep, m, L.ax, L.ay, L.az, L.b, (uint8_t)q8);
+            store_site<false>(pad, rep, m, bx, by, bz, bb, (uint8_t)p8);
+        }
         win[L.la] = (uint8_t)q8;
         win[L.lb] = (uint8_t)p8;
         if constexpr (Geo::rows) {
@@ -920,6 +943,54 @@ __global__ __launch_bounds__(kBlock) void k_ministep(SweepArgs A)
 // A launch covers mini-steps g .. g + nb - 1 of one group.  MAXB: the largest
 // workgroup the instantiation serves (1024 caps registers at 4 waves/SIMD).
 // ---------------------------------------------------------------------------
+// Copy the window rows a row group's trials can have changed back to the
+// padded copy: for every cell row with an active site at offsets (o_y, o_z),
+// the rows within a partner's reach of it on y and z, each to its own row and
+// to its halo image when it lies within H of a face.  Whole padded rows go
+// out, x-images included (the trials keep those current in the window).  No
+// other workgroup of the launch changes these rows (their cells' active rows
+// lie at least a cell edge away), so writing back bytes that did not change
+// is harmless.  One wave per row, 16 bytes per lane.
+template <int LAT, class Geo>
+__device__ __forceinline__ void rows_writeback(const SweepArgs& A, const RepDev& rep, const TileGeom& tg, int oy,
+                                               int oz, uint8_t* pad, const uint8_t* win)
+{
+    constexpr Geometry G = kGeom[LAT];
+    constexpr int PLO = partner_reach(G, false), NP = partner_reach(G, true) - PLO + 1;
+    const int LP = Geo::LP(A), WY = Geo::WY(A);
+    const int n16 = rep.prowp >> 4;
+    const int ky = (tg.c1[1] - tg.c0[1]) * NP, kz = (tg.c1[2] - tg.c0[2]) * NP;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwaves = Geo::block(A) >> 6;
+    const int lane = threadIdx.x & 63;
+    const int Ly = rep.L[1], Lz = rep.L[2];
+    const int64_t prowp = rep.prowp, plane = (int64_t)rep.prows * prowp;
+    for (int i = wave; i < ky * kz; i += nwaves) {
+        const int iy = i % ky, iz = i / ky;
+        const int cy = tg.c0[1] + iy / NP, cz = tg.c0[2] + iz / NP;
+        const int y0 = cell_origin<Geo>(A, rep, 1, cy), z0 = cell_origin<Geo>(A, rep, 2, cz);
+        if (cell_origin<Geo>(A, rep, 1, cy + 1) - y0 <= oy || cell_origin<Geo>(A, rep, 2, cz + 1) - z0 <= oz)
+            continue;  // no active site in this cell
+        const int y = y0 + oy + iy % NP + PLO, z = z0 + oz + iz % NP + PLO;  // in [-1, L]
+        const uint8_t* src = win + ((z - tg.w0[2]) * WY + (y - tg.w0[1])) * LP;
+        const int yr = y < 0 ? y + Ly : (y >= Ly ? y - Ly : y);
+        const int zr = z < 0 ? z + Lz : (z >= Lz ? z - Lz : z);
+        const int yi = yr < kHalo ? yr + Ly : (yr >= Ly - kHalo ? yr - Ly : yr);  // image, or yr itself
+        const int zi = zr < kHalo ? zr + Lz : (zr >= Lz - kHalo ? zr - Lz : zr);
+        uint8_t* d00 = pad + (zr + kHalo) * plane + (yr + kHalo) * prowp;
+        uint8_t* d01 = pad + (zr + kHalo) * plane + (yi + kHalo) * prowp;
+        uint8_t* d10 = pad + (zi + kHalo) * plane + (yr + kHalo) * prowp;
+        uint8_t* d11 = pad + (zi + kHalo) * plane + (yi + kHalo) * prowp;
+        for (int c = lane; c < n16; c += 64) {
+            const uint4 v = *(const uint4*)(src + 16 * c);
+            *(uint4*)(d00 + 16 * c) = v;
+            if (yi != yr) *(uint4*)(d01 + 16 * c) = v;
+            if (zi != zr) *(uint4*)(d10 + 16 * c) = v;
+            if (yi != yr && zi != zr) *(uint4*)(d11 + 16 * c) = v;
+        }
+    }
+}
+
 template <int LAT, int E, class Geo, int MAXB>
 __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
 {
@@ -1019,6 +1090,8 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
             ++ox;
             __syncthreads();  // the next offset's trials read what this one wrote
         }
+        __syncthreads();  // every trial's window writes are visible
+        rows_writeback<LAT, Geo>(A, rep, tg, oy, oz, A.ws + rep.pad_off, win);
     }
     flush_stats(A, r_stats, st);
 }
