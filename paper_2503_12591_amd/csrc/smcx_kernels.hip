@@ -138,6 +138,24 @@ __device__ __forceinline__ uint32_t shl1_add(uint32_t sh, uint32_t acc)
 
 __device__ __forceinline__ uint64_t shl1_add(uint32_t sh, uint64_t acc) { return acc + ((uint64_t)1 << sh); }
 
+// Four of them in one asm block: the compiler pads every inline asm that
+// writes a VGPR with a wait state, so a block per neighbour cost one per add.
+__device__ __forceinline__ uint32_t shl1_add4(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t acc)
+{
+    uint32_t r;
+    asm("v_lshl_add_u32 %0, 1, %1, %5\n\t"
+        "v_lshl_add_u32 %0, 1, %2, %0\n\t"
+        "v_lshl_add_u32 %0, 1, %3, %0\n\t"
+        "v_lshl_add_u32 %0, 1, %4, %0"
+        : "=&v"(r)
+        : "v"(a), "v"(b), "v"(c), "v"(d), "v"(acc));
+    return r;
+}
+__device__ __forceinline__ uint64_t shl1_add4(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint64_t acc)
+{
+    return shl1_add(d, shl1_add(c, shl1_add(b, shl1_add(a, acc))));
+}
+
 // Packed neighbour counters of a basis-B site at LDS byte `base`: A[s] gets
 // 1 << (8 * species) per neighbour of shell s.  Offsets are compile-time
 // displacements times the launch-uniform window pitches.
@@ -205,8 +223,11 @@ __device__ __forceinline__ void count_uniform(const uint8_t* win, int base, int 
                 const int off = nb.dz * PL + nb.dy * LP + XS * nb.dx + BS * (nb.bt - B);
                 v[n] = w[off - lo];
             }
+            const int Z4 = G.Z[s] & ~3;
 #pragma unroll
-            for (int n = 0; n < G.Z[s]; ++n) acc = shl1_add(v[n], acc);
+            for (int n = 0; n < Z4; n += 4) acc = shl1_add4(v[n], v[n + 1], v[n + 2], v[n + 3], acc);
+#pragma unroll
+            for (int n = Z4; n < G.Z[s]; ++n) acc = shl1_add(v[n], acc);
         }
         A[s] = acc;
     }
@@ -590,10 +611,30 @@ __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& re
         acc = true;
     } else {
         const double x = beta * dE;
-        const double P = exp(-x);
-        const double u = (double)(((uint64_t)L.w1 << 21) | (uint64_t)(L.w2 >> 11)) * 0x1p-53;
-        acc = u < P;
-        tie = fabs(u - P) < 1e-12;
+        // A float estimate settles u < exp(-x) whenever u lies farther from
+        // it than the estimate's error: the binary64 test then gives the same
+        // answer and the trial is no near-tie.  u = (w1 2^21 + (w2 >> 11))
+        // 2^-53 lies in [w1 2^-32, (w1 + 1) 2^-32).  For x <= 30, rounding x
+        // and x log2(e) to float moves the exponent by < 8e-6, so exp2 is off
+        // by < 6e-6 relative (plus an ulp or two of v_exp_f32); the margin
+        // is 1e-4 relative plus 1e-9 for u's truncation and rounding.
+        bool settled = false;
+        if (x > 30.0) {
+            // exp(-x) < 1e-13, while u >= 2^-32 unless w1 == 0
+            settled = L.w1 != 0;
+            acc = false;
+        } else {
+            const float uf = (float)L.w1 * 0x1p-32f;
+            const float Pf = __builtin_amdgcn_exp2f((float)x * -1.44269504f);
+            settled = fabsf(uf - Pf) > 1e-4f * Pf + 1e-9f;
+            acc = uf < Pf;
+        }
+        if (!settled) {
+            const double P = exp(-x);
+            const double u = (double)(((uint64_t)L.w1 << 21) | (uint64_t)(L.w2 >> 11)) * 0x1p-53;
+            acc = u < P;
+            tie = fabs(u - P) < 1e-12;
+        }
     }
     if (tie) {
         const int slot = atomicAdd(A.tie_count, 1);
@@ -943,6 +984,23 @@ __global__ __launch_bounds__(kBlock) void k_ministep(SweepArgs A)
 // A launch covers mini-steps g .. g + nb - 1 of one group.  MAXB: the largest
 // workgroup the instantiation serves (1024 caps registers at 4 waves/SIMD).
 // ---------------------------------------------------------------------------
+// Trials of basis sites b0 .. b1 - 1 at one site of a lane's link cell, one
+// code path per basis site (no merge of the sites' lane states).
+template <int LAT, int E, class Geo, int B>
+__device__ __forceinline__ void row_trials(int b0, int b1, const SweepArgs& A, const RepDev& rep, const Lds& T,
+                                           uint8_t* win, const TileGeom& tg, int r, uint32_t t, double beta, int ax,
+                                           int ay, int az, Stats& st)
+{
+    if constexpr (B < kGeom[LAT].m) {
+        if (B >= b0 && B < b1) {
+            LaneState<E> L;
+            trial_read<LAT, E, B, Geo>(A, rep, T, win, tg, r, t, ax, ay, az, L);
+            tile_finish<LAT, E, Geo>(A, rep, r, t, beta, T, win, L, st);
+        }
+        row_trials<LAT, E, Geo, B + 1>(b0, b1, A, rep, T, win, tg, r, t, beta, ax, ay, az, st);
+    }
+}
+
 // Copy the window rows a row group's trials can have changed back to the
 // padded copy: for every cell row with an active site at offsets (o_y, o_z),
 // the rows within a partner's reach of it on y and z, each to its own row and
@@ -1077,13 +1135,8 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
         const int tau1 = g0 + gn;
         while (true) {
             const int nbb = min(m - b, tau1 - tau);
-            if (yz && ox < ex) {
-                for (int j = 0; j < nbb; ++j) {
-                    LaneState<E> L;
-                    read_dispatch<LAT, E, Geo>(b + j, A, rep, T, win, tg, r, t, x0 + ox, y0 + oy, z0 + oz, L);
-                    tile_finish<LAT, E, Geo>(A, rep, r, t, beta, T, win, L, st);
-                }
-            }
+            if (yz && ox < ex)
+                row_trials<LAT, E, Geo, 0>(b, b + nbb, A, rep, T, win, tg, r, t, beta, x0 + ox, y0 + oy, z0 + oz, st);
             tau += nbb;
             if (tau >= tau1) break;
             b = 0;
