@@ -1002,49 +1002,45 @@ __device__ __forceinline__ void row_trials(int b0, int b1, const SweepArgs& A, c
 }
 
 // Copy the window rows a row group's trials can have changed back to the
-// padded copy: for every cell row with an active site at offsets (o_y, o_z),
-// the rows within a partner's reach of it on y and z, each to its own row and
-// to its halo image when it lies within H of a face.  Whole padded rows go
-// out, x-images included (the trials keep those current in the window).  No
-// other workgroup of the launch changes these rows (their cells' active rows
-// lie at least a cell edge away), so writing back bytes that did not change
-// is harmless.  One wave per row, 16 bytes per lane.
+// padded copy: for a row of link cells with an active site at (ya, za) on y
+// and z, the rows within a partner's reach of it on both axes, each to its
+// own row and to its halo images when it lies within H of a face.  Whole
+// padded rows go out, x-images included (the trials keep those current in the
+// window).  No other workgroup of the launch changes these rows (their cells'
+// active rows lie at least a cell edge away), so writing back bytes that did
+// not change is harmless.  The T0 lanes of the cell row share its rows, 16
+// bytes per lane and item.
 template <int LAT, class Geo>
-__device__ __forceinline__ void rows_writeback(const SweepArgs& A, const RepDev& rep, const TileGeom& tg, int oy,
-                                               int oz, uint8_t* pad, const uint8_t* win)
+__device__ __forceinline__ void rows_writeback(const SweepArgs& A, const RepDev& rep, const TileGeom& tg, int lx,
+                                               int T0, int ya, int za, uint8_t* pad, const uint8_t* win)
 {
     constexpr Geometry G = kGeom[LAT];
     constexpr int PLO = partner_reach(G, false), NP = partner_reach(G, true) - PLO + 1;
     const int LP = Geo::LP(A), WY = Geo::WY(A);
     const int n16 = rep.prowp >> 4;
-    const int ky = (tg.c1[1] - tg.c0[1]) * NP, kz = (tg.c1[2] - tg.c0[2]) * NP;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nwaves = Geo::block(A) >> 6;
-    const int lane = threadIdx.x & 63;
+    const int items = NP * NP * n16;
     const int Ly = rep.L[1], Lz = rep.L[2];
     const int64_t prowp = rep.prowp, plane = (int64_t)rep.prows * prowp;
-    for (int i = wave; i < ky * kz; i += nwaves) {
-        const int iy = i % ky, iz = i / ky;
-        const int cy = tg.c0[1] + iy / NP, cz = tg.c0[2] + iz / NP;
-        const int y0 = cell_origin<Geo>(A, rep, 1, cy), z0 = cell_origin<Geo>(A, rep, 2, cz);
-        if (cell_origin<Geo>(A, rep, 1, cy + 1) - y0 <= oy || cell_origin<Geo>(A, rep, 2, cz + 1) - z0 <= oz)
-            continue;  // no active site in this cell
-        const int y = y0 + oy + iy % NP + PLO, z = z0 + oz + iz % NP + PLO;  // in [-1, L]
-        const uint8_t* src = win + ((z - tg.w0[2]) * WY + (y - tg.w0[1])) * LP;
+    // item k: row d = k / n16 of the NP x NP candidates, chunk c = k % n16
+    int d = lx / n16, c = lx - d * n16;
+    const int dd = T0 / n16, dc = T0 - dd * n16;
+    for (int k = lx; k < items; k += T0) {
+        const int y = ya + d % NP + PLO, z = za + d / NP + PLO;  // in [-1, L]
+        const uint4 v = *(const uint4*)(win + ((z - tg.w0[2]) * WY + (y - tg.w0[1])) * LP + 16 * c);
         const int yr = y < 0 ? y + Ly : (y >= Ly ? y - Ly : y);
         const int zr = z < 0 ? z + Lz : (z >= Lz ? z - Lz : z);
         const int yi = yr < kHalo ? yr + Ly : (yr >= Ly - kHalo ? yr - Ly : yr);  // image, or yr itself
         const int zi = zr < kHalo ? zr + Lz : (zr >= Lz - kHalo ? zr - Lz : zr);
-        uint8_t* d00 = pad + (zr + kHalo) * plane + (yr + kHalo) * prowp;
-        uint8_t* d01 = pad + (zr + kHalo) * plane + (yi + kHalo) * prowp;
-        uint8_t* d10 = pad + (zi + kHalo) * plane + (yr + kHalo) * prowp;
-        uint8_t* d11 = pad + (zi + kHalo) * plane + (yi + kHalo) * prowp;
-        for (int c = lane; c < n16; c += 64) {
-            const uint4 v = *(const uint4*)(src + 16 * c);
-            *(uint4*)(d00 + 16 * c) = v;
-            if (yi != yr) *(uint4*)(d01 + 16 * c) = v;
-            if (zi != zr) *(uint4*)(d10 + 16 * c) = v;
-            if (yi != yr && zi != zr) *(uint4*)(d11 + 16 * c) = v;
+        uint8_t* col = pad + 16 * c;
+        *(uint4*)(col + (zr + kHalo) * plane + (yr + kHalo) * prowp) = v;
+        if (yi != yr) *(uint4*)(col + (zr + kHalo) * plane + (yi + kHalo) * prowp) = v;
+        if (zi != zr) *(uint4*)(col + (zi + kHalo) * plane + (yr + kHalo) * prowp) = v;
+        if (yi != yr && zi != zr) *(uint4*)(col + (zi + kHalo) * plane + (yi + kHalo) * prowp) = v;
+        c += dc;
+        d += dd;
+        if (c >= n16) {
+            c -= n16;
+            ++d;
         }
     }
 }
@@ -1113,17 +1109,22 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
         stage_async<LAT, Geo>(A, rep, tg, A.ws + rep.pad_off, win);
         // this lane's cell while the loads fly
         const int cx = lx, cy = tg.c0[1] + ly, cz = tg.c0[2] + lz;
-        const bool in = lz < T2 && cx < tg.c1[0] && cy < tg.c1[1] && cz < tg.c1[2];
+        const bool row_in = lz < T2 && cy < tg.c1[1] && cz < tg.c1[2];
+        const bool in = row_in && cx < tg.c1[0];
         int x0 = 0, ex = 0, y0 = 0, ey = 0, z0 = 0, ez = 0;
-        if (in) {
-            x0 = cell_origin<Geo>(A, rep, 0, cx);
-            ex = cell_origin<Geo>(A, rep, 0, cx + 1) - x0;
+        if (row_in) {
             y0 = cell_origin<Geo>(A, rep, 1, cy);
             ey = cell_origin<Geo>(A, rep, 1, cy + 1) - y0;
             z0 = cell_origin<Geo>(A, rep, 2, cz);
             ez = cell_origin<Geo>(A, rep, 2, cz + 1) - z0;
         }
-        const bool yz = in && oy < ey && oz < ez;
+        if (in) {
+            x0 = cell_origin<Geo>(A, rep, 0, cx);
+            ex = cell_origin<Geo>(A, rep, 0, cx + 1) - x0;
+        }
+        // the cell row has active sites at (o_y, o_z)
+        const bool row_yz = row_in && oy < ey && oz < ez;
+        const bool yz = in && row_yz;
         const double beta = ld_const(A.beta, r);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
@@ -1144,7 +1145,7 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
             __syncthreads();  // the next offset's trials read what this one wrote
         }
         __syncthreads();  // every trial's window writes are visible
-        rows_writeback<LAT, Geo>(A, rep, tg, oy, oz, A.ws + rep.pad_off, win);
+        if (row_yz) rows_writeback<LAT, Geo>(A, rep, tg, lx, T0, y0 + oy, z0 + oz, A.ws + rep.pad_off, win);
     }
     flush_stats(A, r_stats, st);
 }
