@@ -75,6 +75,7 @@ def lib():
         L.or_run_ministeps.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, p, p, u64, u32, u32,
                                        i32, i32, dbl, p, i32, p, p, i32, p, i32]
         L.or_max_threads.argtypes = []
+        L.or_exchange.argtypes = [C.c_int, p, p, p, u64, u32, p, i32, p, p, i32, p]
         _lib = L
     return _lib
 
@@ -238,3 +239,63 @@ def run_ministeps(lattice, dims, K, S, cells, occ: np.ndarray, V, seed: int, bet
 
 def max_threads() -> int:
     return int(lib().or_max_threads())
+
+
+def exchange(E, beta_slot, rep_at, seed: int, round_: int, replay=None, stats=None,
+             tie_cap: int = 64):
+    """One replica-exchange round (``or_exchange``).  rep_at (int32, slot ->
+    replica) and stats ([R-1][2] int64: attempts, acceptances per slot pair)
+    are updated in place.  Returns (ties, n_ties)."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    beta_slot = np.ascontiguousarray(beta_slot, dtype=np.float64)
+    assert rep_at.dtype == np.int32 and rep_at.flags.c_contiguous
+    R = len(rep_at)
+    if stats is None:
+        stats = np.zeros((max(R - 1, 1), 2), np.int64)
+    assert stats.dtype == np.int64 and stats.flags.c_contiguous
+    if replay is None:
+        replay = np.zeros(0, TIE_DTYPE)
+    replay = np.ascontiguousarray(replay, dtype=TIE_DTYPE)
+    ties = np.zeros(max(tie_cap, 1), TIE_DTYPE)
+    n_ties = np.zeros(1, np.int32)
+    rc = lib().or_exchange(R, _ptr(E), _ptr(beta_slot), _ptr(rep_at), seed, round_, _ptr(replay),
+                           len(replay), _ptr(stats), _ptr(ties), tie_cap, _ptr(n_ties))
+    if rc != 0:
+        raise ValueError("or_exchange failed (rep_at is not a slot -> replica map)")
+    nt = int(n_ties[0])
+    return ties[:min(nt, tie_cap)].copy(), nt
+
+
+def tempering(lattice, dims, K, S, cells, occs, V, seed: int, beta_slot, n_rounds: int,
+              sweeps_per_round: int, first_round: int = 0, rep_at=None, replay=None,
+              nthreads: int = 1):
+    """Parallel tempering of R replicas of one lattice (``occs``: list of R
+    uint8 arrays, updated in place).  Round j: every replica r runs sweeps
+    j n .. j n + n - 1 (n = sweeps_per_round) at the beta of its slot, then
+    the energies from fresh pair counts decide one exchange round j.
+
+    Returns dict(rep_at, stats [R][3], xstats [R-1][2], ties (sweep and
+    exchange near-ties), energies [n_rounds][R])."""
+    R = len(occs)
+    rep_at = np.arange(R, dtype=np.int32) if rep_at is None else np.array(rep_at, np.int32)
+    beta_slot = np.asarray(beta_slot, np.float64)
+    stats = np.zeros((R, 3), np.int64)
+    xstats = np.zeros((max(R - 1, 1), 2), np.int64)
+    ties, energies = [], []
+    n = sweeps_per_round
+    for j in range(first_round, first_round + n_rounds):
+        slot_of = np.empty(R, np.int64)
+        slot_of[rep_at] = np.arange(R)
+        for r in range(R):
+            res = run(lattice, dims, K, S, cells, occs[r], V, seed,
+                      np.full(n, beta_slot[slot_of[r]]), first_sweep=j * n, replica=r,
+                      replay=replay, nthreads=nthreads)
+            stats[r] += res.stats
+            ties.append(res.ties)
+        E = np.array([energy(pair_counts(lattice, dims, K, S, occs[r]), V) for r in range(R)])
+        energies.append(E)
+        t, _ = exchange(E, beta_slot, rep_at, seed, j, replay=replay, stats=xstats)
+        ties.append(t)
+    return dict(rep_at=rep_at, stats=stats, xstats=xstats,
+                ties=np.concatenate(ties) if ties else np.zeros(0, TIE_DTYPE),
+                energies=np.array(energies))

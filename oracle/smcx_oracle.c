@@ -696,3 +696,74 @@ int or_max_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Replica exchange between temperature slots                                */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * One round of replica exchange (parallel tempering: Swendsen and Wang, PRL
+ * 57 (1986) 2607; Geyer 1991; Hukushima and Nemoto, JPSJ 65 (1996) 1604) over
+ * R replicas of one lattice held in R temperature slots.  The paper runs its
+ * temperatures as independent chains (Supplementary, parallelization
+ * opportunities); exchanging configurations between neighbouring
+ * temperatures is the textbook extension of such a ladder.
+ *
+ * rep_at[i] is the replica held by slot i (inverse temperature
+ * beta_slot[i]); E[r] is the energy of replica r.  Round j pairs slots
+ * (i, i + 1) for i = j mod 2, j mod 2 + 2, ... while i + 1 < R.  With
+ * a = rep_at[i], b = rep_at[i + 1], the joint weight of the two slots changes
+ * by exp(x), x = (beta_slot[i] - beta_slot[i + 1]) * (E[a] - E[b]), when they
+ * trade replicas, so the trade is accepted when x >= 0 and otherwise when
+ * u < exp(x), u the 53-bit uniform of Philox4x32-10 on counter
+ * (i, 0, j, 0xffffffff) under the run's key (no trial uses replica index
+ * 0xffffffff).  |u - exp(x)| < 1e-12 is a near-tie: it is logged as
+ * {replica -1, sweep j, site i, decision}, and a replay entry with those
+ * keys overrides the decision.  Accepted pairs swap rep_at[i] and
+ * rep_at[i + 1].  stats[2 i] counts the attempts of pair i, stats[2 i + 1]
+ * its acceptances.  Returns OR_EARG if rep_at holds an index outside [0, R).
+ */
+int or_exchange(int R, const double *E, const double *beta_slot, int32_t *rep_at, uint64_t seed,
+                uint32_t round, const or_tie *replay, int32_t n_replay, int64_t *stats, or_tie *ties,
+                int32_t tie_cap, int32_t *n_ties)
+{
+    for (int i = 0; i < R; ++i)
+        if (rep_at[i] < 0 || rep_at[i] >= R) return OR_EARG;
+    or_replay rp = {replay, n_replay};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int i = (int)(round & 1u); i + 1 < R; i += 2) {
+        int a = rep_at[i], b = rep_at[i + 1];
+        double x = (beta_slot[i] - beta_slot[i + 1]) * (E[a] - E[b]);
+        int accept;
+        if (x >= 0.0) {
+            accept = 1;
+        } else {
+            uint32_t ctr[4] = {(uint32_t)i, 0u, round, 0xffffffffu};
+            uint32_t w[4];
+            or_philox4x32_10(ctr, key, w);
+            double P = exp(x);
+            double u = (double)(((uint64_t)w[1] << 21) | (uint64_t)(w[2] >> 11)) * 0x1p-53;
+            accept = u < P;
+            if (fabs(u - P) < 1e-12) {
+                int dec;
+                if (replay_lookup(&rp, -1, round, i, &dec)) accept = dec;
+                if (*n_ties < tie_cap) {
+                    or_tie *e = &ties[*n_ties];
+                    e->replica = -1;
+                    e->sweep = round;
+                    e->site = i;
+                    e->decision = accept;
+                    e->pad = 0;
+                }
+                *n_ties += 1;
+            }
+        }
+        stats[2 * i] += 1;
+        if (accept) {
+            stats[2 * i + 1] += 1;
+            rep_at[i] = b;
+            rep_at[i + 1] = a;
+        }
+    }
+    return OR_OK;
+}

@@ -37,6 +37,15 @@ MUTANTS = [
      ["test_oracle_geometry.py::test_textbook_coordination"]),
     ("link-cell rule one short", "while (!(2 * ell > 1 + reach)) ++ell;", "while (!(2 * ell > reach)) ++ell;",
      ["test_oracle_geometry.py::test_link_cell_rule_reproduces_paper", "test_oracle_geometry.py::test_link_cell_rule_is_tight"]),
+    ("exchange energy difference reversed", "double x = (beta_slot[i] - beta_slot[i + 1]) * (E[a] - E[b]);",
+     "double x = (beta_slot[i] - beta_slot[i + 1]) * (E[b] - E[a]);",
+     ["test_oracle_tempering.py::test_exchange_acceptance_frequency",
+      "test_oracle_tempering.py::test_tempering_slots_sample_their_temperature"]),
+    ("exchange factor inverted", "double P = exp(x);", "double P = exp(-x);",
+     ["test_oracle_tempering.py::test_exchange_acceptance_frequency"]),
+    ("exchange ignores the round parity", "for (int i = (int)(round & 1u); i + 1 < R; i += 2)",
+     "for (int i = 0; i + 1 < R; i += 2)",
+     ["test_oracle_tempering.py::test_exchange_special_cases"]),
 ]
 
 
