@@ -209,6 +209,44 @@ int smcx_energy(smcx_lattice *h, int64_t *counts_dev, double *E_host, void *stre
  * Synchronises the stream. */
 int smcx_sro(smcx_lattice *h, int64_t *counts_dev, double *alpha_host, void *stream);
 
+/* Energies as smcx_energy, left on the device: counts_dev [R][S][K][K] int64
+ * is overwritten with the pair counts, E_dev [R] binary64 receives
+ * E[r] = 1/2 sum_{s,k,l} C V (s, k, l ascending, the same rounding as
+ * smcx_energy).  Asynchronous on `stream`, no host synchronisation (so it
+ * can be recorded in a graph).  (Eq. Total_EPI.) */
+int smcx_energy_dev(smcx_lattice *h, int64_t *counts_dev, double *E_dev, void *stream);
+
+/* One round of replica exchange (parallel tempering) between R temperature
+ * slots, for replicas of one size.  Not part of the paper, whose
+ * temperatures run as independent chains (Supplementary, parallelization
+ * opportunities); the rule is the textbook one (Swendsen and Wang 1986;
+ * Hukushima and Nemoto 1996).
+ *   beta_slot_dev [R] binary64: inverse temperature of slot i (any order).
+ *   rep_at_dev [R] int32, in/out: the replica held by slot i, a permutation
+ *     of 0 .. R-1 (start from the identity).  Entries outside [0, R) leave
+ *     their pair, and their replica's beta, untouched.
+ *   Round `round` computes every replica's energy (counts_dev, E_dev as for
+ *   smcx_energy_dev) and visits the slot pairs (i, i + 1), i = round mod 2,
+ *   round mod 2 + 2, ...: with a = rep_at[i], b = rep_at[i + 1] and
+ *   x = (beta_slot[i] - beta_slot[i + 1]) (E[a] - E[b]) the slots trade their
+ *   replicas when x >= 0, else when u < exp(x), u the 53-bit uniform of
+ *   Philox4x32-10 with key `seed` on counter (i, 0, round, 0xffffffff) (no
+ *   trial uses replica index 0xffffffff).  |u - exp(x)| < 1e-12 is a
+ *   near-tie, appended to ties_dev as {replica -1, sweep round, site i,
+ *   decision} (tie_count_dev counts past tie_cap as for smcx_sweep).
+ *   xstats_dev [R-1][2] int64, accumulated: attempts and trades of pair i.
+ *   beta_dev [n_beta_rows][R] binary64, written: every row gets each
+ *     replica's new inverse temperature, ready as the beta argument of the
+ *     next smcx_sweep of n_beta_rows sweeps (n_beta_rows may be 0).
+ * All pointers are device memory owned by the caller.  Asynchronous, no
+ * host synchronisation, no allocation.  Errors: SMCX_E_INVALID_ARG for
+ * missing buffers, round < 0 or replicas of different sizes;
+ * SMCX_E_NOT_READY before smcx_set_epi. */
+int smcx_exchange(smcx_lattice *h, int32_t round, uint64_t seed, const double *beta_slot_dev,
+                  int32_t *rep_at_dev, double *beta_dev, int32_t n_beta_rows, int64_t *counts_dev,
+                  double *E_dev, int64_t *xstats_dev, smcx_tie *ties_dev, int32_t tie_cap,
+                  int32_t *tie_count_dev, void *stream);
+
 /* Stateless batched pair counts for B configurations of one geometry:
  * occ_batch_dev device uint8 [B][N] (N = m * dims[0]*dims[1]*dims[2]),
  * counts_dev device int64 [B][S][K][K] (overwritten).  The gradient of

@@ -410,6 +410,12 @@ static double trial_dE(const or_sys *sy, const uint8_t *occ, const double *V, in
     return dE;
 }
 
+/* The 53-bit uniform of a trial or exchange: (w1 2^21 + floor(w2 / 2^11)) 2^-53. */
+static double u53(const uint32_t w[4])
+{
+    return (double)(((uint64_t)w[1] << 21) | (uint64_t)(w[2] >> 11)) * 0x1p-53;
+}
+
 typedef struct {
     const or_tie *replay;
     int32_t n_replay;
@@ -456,7 +462,7 @@ static int do_trial(const or_sys *sy, uint8_t *occ, const double *V, uint64_t se
         } else {
             double x = beta * dE;
             double P = exp(-x);
-            double u = (double)(((uint64_t)w[1] << 21) | (uint64_t)(w[2] >> 11)) * 0x1p-53;
+            double u = u53(w);
             accept = u < P;
             if (fabs(u - P) < 1e-12) {
                 flags |= TR_TIE;
@@ -742,7 +748,7 @@ int or_exchange(int R, const double *E, const double *beta_slot, int32_t *rep_at
             uint32_t w[4];
             or_philox4x32_10(ctr, key, w);
             double P = exp(x);
-            double u = (double)(((uint64_t)w[1] << 21) | (uint64_t)(w[2] >> 11)) * 0x1p-53;
+            double u = u53(w);
             accept = u < P;
             if (fabs(u - P) < 1e-12) {
                 int dec;

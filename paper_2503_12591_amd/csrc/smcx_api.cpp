@@ -97,7 +97,7 @@ struct Plan {
     std::vector<Replica> reps;
     int LP, WY, WZ;
     LdsLayout lds;
-    size_t off_reps, off_origins, off_tileoff, off_offP, off_offB, off_pd, off_D, off_misc, off_pad, total;
+    size_t off_reps, off_origins, off_tileoff, off_offP, off_offB, off_pd, off_D, off_V, off_misc, off_pad, total;
     int n_origins;
     int64_t total_sites, total_tiles;
     int max_nA;
@@ -378,6 +378,7 @@ int make_plan(const smcx_desc* d, Plan& P)
     P.off_offB = o; o = align256(o + sizeof(int32_t) * P.m * P.Z1);
     P.off_pd = o; o = align256(o + 4 * P.m * P.Z1);
     P.off_D = o; o = align256(o + sizeof(double) * P.K * P.K * P.S * P.K);
+    P.off_V = o; o = align256(o + sizeof(double) * P.S * P.K * P.K);
     P.off_misc = o; o = align256(o + 256);
     P.off_rowoff = o; o = align256(o + sizeof(int64_t) * (P.R + 1));
     P.off_offP_r = o; o = align256(o + sizeof(int16_t) * P.m * P.Z1 * P.sumZ);
@@ -744,6 +745,7 @@ int smcx_set_epi(smcx_lattice* h, const double* V, void* stream)
                     h->Dhost[((s * K + t) * K + p) * K + q] = V[(s * K + q) * K + t] - V[(s * K + p) * K + t];
     hipStream_t st = (hipStream_t)stream;
     SMCX_HIP(hipMemcpyAsync(h->ws + P.off_D, h->Dhost.data(), sizeof(double) * h->Dhost.size(), hipMemcpyHostToDevice, st));
+    SMCX_HIP(hipMemcpyAsync(h->ws + P.off_V, h->V.data(), sizeof(double) * h->V.size(), hipMemcpyHostToDevice, st));
     SMCX_HIP(hipStreamSynchronize(st));
     h->epi_set = true;
     return SMCX_OK;
@@ -926,6 +928,41 @@ int smcx_energy(smcx_lattice* h, int64_t* counts_dev, double* E_host, void* stre
                 }
         E_host[r] = 0.5 * acc;
     }
+    return SMCX_OK;
+}
+
+int smcx_energy_dev(smcx_lattice* h, int64_t* counts_dev, double* E_dev, void* stream)
+{
+    if (int rc = check_handle(h)) return rc;
+    if (!h->epi_set) return fail(SMCX_E_NOT_READY, "smcx_set_epi has not been called");
+    if (!counts_dev || !E_dev) return fail(SMCX_E_INVALID_ARG, "counts_dev and E_dev are required");
+    if (int rc = smcx_pair_counts(h, counts_dev, stream)) return rc;
+    const Plan& P = h->P;
+    SMCX_HIP(launch_energy(counts_dev, (const double*)(h->ws + P.off_V), P.R, P.S * P.K * P.K, E_dev,
+                           (hipStream_t)stream));
+    return SMCX_OK;
+}
+
+int smcx_exchange(smcx_lattice* h, int32_t round, uint64_t seed, const double* beta_slot_dev, int32_t* rep_at_dev,
+                  double* beta_dev, int32_t n_beta_rows, int64_t* counts_dev, double* E_dev, int64_t* xstats_dev,
+                  smcx_tie* ties_dev, int32_t tie_cap, int32_t* tie_count_dev, void* stream)
+{
+    if (int rc = check_handle(h)) return rc;
+    if (!h->epi_set) return fail(SMCX_E_NOT_READY, "smcx_set_epi has not been called");
+    if (round < 0) return fail(SMCX_E_INVALID_ARG, "round must be >= 0");
+    if (!beta_slot_dev || !rep_at_dev || !counts_dev || !E_dev || !xstats_dev || !tie_count_dev)
+        return fail(SMCX_E_INVALID_ARG, "beta_slot, rep_at, counts, E, xstats and tie_count are required");
+    if (n_beta_rows < 0 || (n_beta_rows > 0 && !beta_dev))
+        return fail(SMCX_E_INVALID_ARG, "beta_dev is required when n_beta_rows > 0");
+    if (tie_cap < 0 || (tie_cap > 0 && !ties_dev)) return fail(SMCX_E_INVALID_ARG, "ties_dev required when tie_cap > 0");
+    const Plan& P = h->P;
+    for (const Replica& R : P.reps)
+        for (int a = 0; a < 3; ++a)
+            if (R.L[a] != P.reps[0].L[a])
+                return fail(SMCX_E_INVALID_ARG, "replica exchange needs replicas of one size");
+    if (int rc = smcx_energy_dev(h, counts_dev, E_dev, stream)) return rc;
+    SMCX_HIP(launch_exchange(E_dev, beta_slot_dev, rep_at_dev, P.R, seed, (uint32_t)round, beta_dev, n_beta_rows,
+                             xstats_dev, ties_dev, tie_cap, tie_count_dev, (hipStream_t)stream));
     return SMCX_OK;
 }
 

@@ -1575,6 +1575,95 @@ hipError_t launch_validate(const uint8_t* occ, int64_t n, int K, int32_t* bad, h
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Replica exchange.  k_energy: E_r = 1/2 sum_{s,k,l} C_r[s][k][l] V[s][k][l],
+// accumulated s, k, l ascending in binary64, one thread per replica (the
+// order fixes the rounding, the same as the host-side energy).  k_exchange:
+// one round of trades between neighbouring temperature slots (i, i + 1),
+// i = round mod 2, round mod 2 + 2, ...: with a = rep_at[i], b = rep_at[i+1]
+// and x = (beta_slot[i] - beta_slot[i+1]) (E_a - E_b), the trade is taken
+// when x >= 0, else when u < exp(x) (u from Philox on counter
+// (i, 0, round, 0xffffffff), which no trial uses); near-ties
+// (|u - exp(x)| < 1e-12) go to the tie log as {-1, round, i, decision}.
+// One workgroup: every pair of the round has its own thread, so the pairs'
+// slots, stats and trades never collide.  Then every replica's new beta is
+// written to each of the n_rows rows the next sweeps read.  rep_at entries
+// outside [0, R) leave their pair (and their replica's beta) untouched.
+// ---------------------------------------------------------------------------
+__global__ void k_energy(const int64_t* C, const double* V, int R, int SKK, double* E)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int64_t* c = C + (int64_t)r * SKK;
+    double acc = 0.0;
+    for (int i = 0; i < SKK; ++i) acc = acc + (double)c[i] * V[i];
+    E[r] = 0.5 * acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_exchange(const double* E, const double* beta_slot, int32_t* rep_at, int R,
+                                                     uint64_t seed, uint32_t round, double* beta_rows, int n_rows,
+                                                     int64_t* xstats, smcx_tie* ties, int32_t tie_cap,
+                                                     int32_t* tie_count)
+{
+    for (int i = (int)(round & 1u) + 2 * (int)threadIdx.x; i + 1 < R; i += 2 * (int)blockDim.x) {
+        const int a = rep_at[i], b = rep_at[i + 1];
+        if (a < 0 || a >= R || b < 0 || b >= R) continue;
+        const double x = (beta_slot[i] - beta_slot[i + 1]) * (E[a] - E[b]);
+        bool acc = true, tie = false;
+        if (!(x >= 0.0)) {
+            uint32_t w0, w1, w2, w3;
+            philox4x32_10((uint32_t)i, 0u, round, 0xffffffffu, (uint32_t)seed, (uint32_t)(seed >> 32), w0, w1, w2,
+                          w3);
+            (void)w0;
+            (void)w3;
+            const double P = exp(x);
+            const double u = (double)(((uint64_t)w1 << 21) | (uint64_t)(w2 >> 11)) * 0x1p-53;
+            acc = u < P;
+            tie = fabs(u - P) < 1e-12;
+        }
+        if (tie) {
+            const int slot = atomicAdd(tie_count, 1);
+            if (slot < tie_cap) {
+                smcx_tie e;
+                e.replica = -1;
+                e.sweep = round;
+                e.site = i;
+                e.decision = acc ? 1 : 0;
+                e.pad = 0;
+                ties[slot] = e;
+            }
+        }
+        xstats[2 * i] += 1;
+        if (acc) {
+            xstats[2 * i + 1] += 1;
+            rep_at[i] = b;
+            rep_at[i + 1] = a;
+        }
+    }
+    __syncthreads();  // every trade of the round is in rep_at
+    for (int j = threadIdx.x; j < R; j += blockDim.x) {
+        const int r = rep_at[j];
+        if (r < 0 || r >= R) continue;
+        const double bj = beta_slot[j];
+        for (int row = 0; row < n_rows; ++row) beta_rows[(int64_t)row * R + r] = bj;
+    }
+}
+
+hipError_t launch_energy(const int64_t* C, const double* V, int R, int SKK, double* E, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_energy, dim3((unsigned)((R + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, C, V, R, SKK, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_exchange(const double* E, const double* beta_slot, int32_t* rep_at, int R, uint64_t seed,
+                           uint32_t round, double* beta_rows, int n_rows, int64_t* xstats, smcx_tie* ties,
+                           int32_t tie_cap, int32_t* tie_count, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_exchange, dim3(1), dim3(kBlock), 0, st, E, beta_slot, rep_at, R, seed, round, beta_rows,
+                       n_rows, xstats, ties, tie_cap, tie_count);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st)
 {
     int64_t nb = (n + kBlock - 1) / kBlock;

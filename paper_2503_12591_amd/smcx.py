@@ -29,6 +29,7 @@ EXPORTS = [
     "smcx_pair_counts", "smcx_energy", "smcx_sro", "smcx_energy_backward", "smcx_ladder_capture",
     "smcx_sweep_capture",
     "smcx_graph_launch", "smcx_graph_destroy", "smcx_timing_enable", "smcx_timing_read",
+    "smcx_energy_dev", "smcx_exchange",
 ]
 
 
@@ -76,6 +77,8 @@ def lib():
     L.smcx_graph_destroy.argtypes = [p]
     L.smcx_timing_enable.argtypes = [p, i32]
     L.smcx_timing_read.argtypes = [p, p, p]
+    L.smcx_energy_dev.argtypes = [p, p, p, p]
+    L.smcx_exchange.argtypes = [p, i32, u64, p, p, p, i32, p, p, p, p, i32, p, p]
     _lib = L
     return L
 
@@ -263,6 +266,14 @@ class Lattice:
                                  _stream(self.torch)))
         return E
 
+    def energy_dev(self, E=None):
+        """Energies of every replica into a CUDA float64 tensor [R], no host
+        synchronisation (smcx_energy_dev)."""
+        if E is None:
+            E = self.torch.zeros(self.R, dtype=self.torch.float64, device="cuda")
+        _check(lib().smcx_energy_dev(self.h, _ptr(self.counts), _ptr(E), _stream(self.torch)))
+        return E
+
     def sro(self) -> np.ndarray:
         a = np.zeros((self.R, self.S, self.K, self.K), np.float64)
         _check(lib().smcx_sro(self.h, _ptr(self.counts), a.ctypes.data_as(C.c_void_p),
@@ -281,6 +292,49 @@ class Lattice:
         n = np.zeros(1, np.int64)
         _check(lib().smcx_timing_read(self.h, ms.ctypes.data_as(C.c_void_p), n.ctypes.data_as(C.c_void_p)))
         return float(ms[0]), int(n[0])
+
+
+class Tempering:
+    """Parallel tempering over the R replicas (one size) of a Lattice.
+
+    Round j: every replica runs sweeps j n .. j n + n - 1 (n =
+    sweeps_per_round) at the inverse temperature of the slot holding it, then
+    smcx_exchange trades neighbouring slots' replicas and writes the betas of
+    the next round's sweeps.  Everything stays on the device; rep_at (slot ->
+    replica), E (energies at the last exchange), xstats ([R-1][2] attempts,
+    trades), stats ([R][3] sweep counters) and the shared tie log are CUDA
+    tensors.
+    """
+
+    def __init__(self, lat: Lattice, beta_slot, seed: int, sweeps_per_round: int, mode="auto",
+                 tie_cap: int = 4096):
+        torch = lat.torch
+        R = lat.R
+        self.lat, self.seed, self.n, self.mode, self.tie_cap = lat, seed, sweeps_per_round, mode, tie_cap
+        self.beta_slot = torch.tensor(np.asarray(beta_slot, np.float64).reshape(R), dtype=torch.float64,
+                                      device="cuda")
+        self.rep_at = torch.arange(R, dtype=torch.int32, device="cuda")
+        self.beta_rows = self.beta_slot.repeat(sweeps_per_round, 1).contiguous()
+        self.E = torch.zeros(R, dtype=torch.float64, device="cuda")
+        self.xstats = torch.zeros(max(R - 1, 1) * 2, dtype=torch.int64, device="cuda")
+        self.stats = torch.zeros(R * 3, dtype=torch.int64, device="cuda")
+        self.ties = torch.zeros(max(tie_cap, 1) * TIE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        self.tie_count = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.round = 0
+
+    def run(self, n_rounds: int):
+        lat, torch = self.lat, self.lat.torch
+        for _ in range(n_rounds):
+            lat.sweep(self.n, self.seed, self.beta_rows, first_sweep=self.round * self.n, mode=self.mode,
+                      tie_cap=self.tie_cap, stats=self.stats, ties=self.ties, tie_count=self.tie_count)
+            _check(lib().smcx_exchange(lat.h, self.round, C.c_uint64(self.seed), _ptr(self.beta_slot),
+                                       _ptr(self.rep_at), _ptr(self.beta_rows), self.n, _ptr(lat.counts),
+                                       _ptr(self.E), _ptr(self.xstats), _ptr(self.ties), self.tie_cap,
+                                       _ptr(self.tie_count), _stream(torch)))
+            self.round += 1
+
+    def ties_numpy(self):
+        return Lattice.ties_to_numpy(self.ties, self.tie_count)
 
 
 class LadderGraph:
