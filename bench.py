@@ -223,6 +223,8 @@ def main():
     if not args.no_ladder:
         print("[bench] ladder", file=sys.stderr, flush=True)
         out["ladder"] = ladder_bench(args)
+        print("[bench] tempering", file=sys.stderr, flush=True)
+        out["tempering"] = tempering_bench(args)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(lattice, dims, K, S, cells, occ_host, V, seed, beta,
@@ -316,6 +318,46 @@ def ladder_bench(args):
             "tuned_config": {"tile": best["tile"], "mode": best["mode"], "ell": best["ell"], "rows": best["rows"]},
             "batched_over_plain": batched / res["plain"],
             "batched_over_plain_graph": batched / res["plain_graph"]}
+
+
+def tempering_bench(args, rounds: int = 4, sweeps_per_round: int = 5):
+    """Replica exchange on 256 BCC 32^3 replicas (the ladder's temperatures
+    and EPI): attempted swaps/s of whole rounds (sweeps of every replica at
+    its slot's temperature, then smcx_exchange: pair counts, energies and one
+    round of slot trades), the time of one exchange round on its own, and the
+    fraction of slot trades taken."""
+    import torch
+    from paper_2503_12591_amd import inputs as I
+    from paper_2503_12591_amd import smcx
+    lad = I.tempering_ladder()
+    occ = torch.from_numpy(np.concatenate([lad.occ(r) for r in range(lad.R)])).cuda()
+    N = int(occ.numel())
+    lat = smcx.Lattice(I.BCC, lad.dims(), lad.K, lad.S, occ, ell=4)
+    lat.set_epi(lad.V)
+    pt = smcx.Tempering(lat, lad.betas, seed=0, sweeps_per_round=sweeps_per_round, mode="stream")
+    pt.run(1)  # warm-up round
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    secs = timed(lambda: pt.run(rounds))
+    x0 = pt.xstats.cpu().numpy().reshape(-1, 2).sum(axis=0)
+    # one exchange round alone (it only permutes slots; the next sweeps would read its betas)
+    ex = timed(lambda: smcx._check(smcx.lib().smcx_exchange(
+        lat.h, pt.round, 0, smcx._ptr(pt.beta_slot), smcx._ptr(pt.rep_at), smcx._ptr(pt.beta_rows),
+        pt.n, smcx._ptr(lat.counts), smcx._ptr(pt.E), smcx._ptr(pt.xstats), smcx._ptr(pt.ties),
+        pt.tie_cap, smcx._ptr(pt.tie_count), smcx._stream(torch))))
+    lat.close()
+    return {"workload": "bcc_tempering256_L32_k4_s4", "sites": N, "rounds": rounds,
+            "sweeps_per_round": sweeps_per_round, "unit": "attempted swaps/s",
+            "swaps_per_s": rounds * sweeps_per_round * N / secs, "exchange_round_us": ex * 1e6,
+            "trade_fraction": float(x0[1] / max(x0[0], 1))}
 
 
 def algorithmic_bytes_per_launch(cells, N, m, launches_per_sweep):

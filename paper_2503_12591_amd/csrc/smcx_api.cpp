@@ -891,6 +891,15 @@ int smcx_pair_counts(smcx_lattice* h, int64_t* counts_dev, void* stream)
     hipStream_t st = (hipStream_t)stream;
     const int64_t per = (int64_t)P.S * P.K * P.K;
     SMCX_HIP(launch_fill_i64(counts_dev, per * P.R, 0, st));
+    // replicas of one size lie back to back: one batched launch
+    bool one_size = P.R <= 65535;
+    for (const Replica& R : P.reps)
+        for (int a = 0; a < 3; ++a) one_size &= R.L[a] == P.reps[0].L[a];
+    if (one_size) {
+        const Replica& R = P.reps[0];
+        SMCX_HIP(launch_pair_counts(P.lattice, P.K, P.S, h->occ, R.N, R.L, P.R, counts_dev, st));
+        return SMCX_OK;
+    }
     for (int r = 0; r < P.R; ++r) {
         const Replica& R = P.reps[r];
         SMCX_HIP(launch_pair_counts(P.lattice, P.K, P.S, h->occ + R.occ_off, R.N, R.L, 1, counts_dev + per * r, st));

@@ -1699,7 +1699,10 @@ hipError_t launch_pair_counts(int lattice, int K, int S, const uint8_t* occ, int
         const bool wide = L[0] >= 48;
         const int TX = wide ? 64 : 16, TY = kBlock / TX;
         const int64_t ntiles = (int64_t)((L[0] + TX - 1) / TX) * ((L[1] + TY - 1) / TY) * ((L[2] + 15) / 16);
-        const int tpb = 2048 / (m * 16);
+        // up to 2048 / (16 m) tiles per workgroup, fewer when the batch has
+        // too few tiles to give the chip ~2048 workgroups
+        const int64_t tpb_max = 2048 / (m * 16);
+        const int tpb = (int)std::max<int64_t>(1, std::min<int64_t>(tpb_max, (ntiles * B + 2047) / 2048));
         const int64_t nbx = (ntiles + tpb - 1) / tpb;
         if (nbx > 0x7fffffff || B > 65535) return hipErrorInvalidValue;
         const dim3 g((unsigned)nbx, (unsigned)B), b(kBlock);

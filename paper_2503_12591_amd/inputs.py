@@ -199,6 +199,14 @@ def c4a_ladder(R: int = 256, n_sweeps: int = 1000, lo: int = 16, hi: int = 48) -
     return Ladder(edges.astype(np.int32), 4, 4, epi(4, 4, 0.02, seed=4), beta_of_T(T), n_sweeps)
 
 
+def tempering_ladder(R: int = 256, edge: int = 32, n_sweeps: int = 1000) -> Ladder:
+    """R cubic BCC replicas of one edge for replica exchange (the ladder's
+    temperatures and EPI; the edge is the mean of its 16..48 range)."""
+    r = np.arange(R, dtype=np.float64)
+    T = 300.0 * 10.0 ** (r / max(R - 1, 1))
+    return Ladder(np.full(R, edge, np.int32), 4, 4, epi(4, 4, 0.02, seed=4), beta_of_T(T), n_sweeps)
+
+
 def c4b_fit_set(B: int = 4096, edge: int = 16):
     """Random equiatomic BCC configurations and a seeded teacher V*."""
     dims = (edge, edge, edge)
