@@ -76,6 +76,8 @@ def lib():
                                        i32, i32, dbl, p, i32, p, p, i32, p, i32]
         L.or_max_threads.argtypes = []
         L.or_exchange.argtypes = [C.c_int, p, p, p, u64, u32, p, i32, p, p, i32, p]
+        L.or_heat_capacity.argtypes = [C.c_int, p, dbl, i64]
+        L.or_heat_capacity.restype = dbl
         _lib = L
     return _lib
 
@@ -299,3 +301,43 @@ def tempering(lattice, dims, K, S, cells, occs, V, seed: int, beta_slot, n_round
     return dict(rep_at=rep_at, stats=stats, xstats=xstats,
                 ties=np.concatenate(ties) if ties else np.zeros(0, TIE_DTYPE),
                 energies=np.array(energies))
+
+
+def heat_capacity(E, beta: float, N: int) -> float:
+    """Heat capacity per site in units of k_B from recorded energies
+    (``or_heat_capacity``: beta^2 Var(E) / N, two-pass, population variance)."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    return float(lib().or_heat_capacity(len(E), _ptr(E), float(beta), int(N)))
+
+
+def anneal(lattice, dims, K, S, cells, occ: np.ndarray, V, seed: int, beta_steps, warmup: int,
+           record: int, first_sweep: int = 0, replica: int = 0, replay=None, nthreads: int = 1):
+    """Stepwise anneal of one replica (``occ`` updated in place): step s runs
+    ``warmup`` sweeps at beta_steps[s], then ``record`` sweeps each followed by
+    the energy; the step's heat capacity comes from its recorded energies.
+    Sweep indices continue from first_sweep.  Returns dict(E [n_steps][record],
+    cv [n_steps], stats [3], ties)."""
+    beta_steps = np.asarray(beta_steps, np.float64)
+    n_steps = len(beta_steps)
+    N = len(occ)
+    E = np.zeros((n_steps, record), np.float64)
+    cv = np.zeros(n_steps, np.float64)
+    stats = np.zeros(3, np.int64)
+    ties = []
+    for s, b in enumerate(beta_steps):
+        t0 = first_sweep + s * (warmup + record)
+        if warmup:
+            res = run(lattice, dims, K, S, cells, occ, V, seed, np.full(warmup, b), first_sweep=t0,
+                      replica=replica, replay=replay, nthreads=nthreads)
+            stats += res.stats
+            ties.append(res.ties)
+        for j in range(record):
+            res = run(lattice, dims, K, S, cells, occ, V, seed, [b], first_sweep=t0 + warmup + j,
+                      replica=replica, replay=replay, nthreads=nthreads)
+            stats += res.stats
+            ties.append(res.ties)
+            E[s, j] = energy(pair_counts(lattice, dims, K, S, occ), V)
+        if record:
+            cv[s] = heat_capacity(E[s], b, N)
+    return dict(E=E, cv=cv, stats=stats,
+                ties=np.concatenate(ties) if ties else np.zeros(0, TIE_DTYPE))

@@ -773,3 +773,29 @@ int or_exchange(int R, const double *E, const double *beta_slot, int32_t *rep_at
     }
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Heat capacity from energy fluctuations                                    */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Heat capacity per site, in units of k_B, from n energies recorded at one
+ * inverse temperature beta: c = beta^2 (<E^2> - <E>^2) / N (the fluctuation
+ * formula of the canonical ensemble; the paper reads its specific-heat peaks
+ * off annealing runs, Results on the phase transitions and Methods on the
+ * annealing protocol).  Two passes in binary64, j ascending:
+ * m = (sum E_j) / n, v = (sum (E_j - m)^2) / n, c = (beta beta) v / N.
+ */
+double or_heat_capacity(int n, const double *E, double beta, int64_t N)
+{
+    double m = 0.0;
+    for (int j = 0; j < n; ++j) m = m + E[j];
+    m = m / (double)n;
+    double v = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double d = E[j] - m;
+        v = v + d * d;
+    }
+    v = v / (double)n;
+    return beta * beta * v / (double)N;
+}

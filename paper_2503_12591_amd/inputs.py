@@ -99,6 +99,13 @@ def linear_anneal(T0: float, T1: float, n: int) -> np.ndarray:
     return T0 + (T1 - T0) * t / (n - 1)
 
 
+def stepwise_temperatures(T0: float = 2000.0, T1: float = 300.0, dT: float = 50.0) -> np.ndarray:
+    """Annealing temperatures T0, T0 - dT, ... down to T1 (inclusive when it
+    falls on the grid): the paper starts at 2000 K and lowers T by 50 K."""
+    n = int(np.floor((T0 - T1) / dT + 1e-9)) + 1
+    return T0 - dT * np.arange(n, dtype=np.float64)
+
+
 def n_sites(lattice: int, dims) -> int:
     return int(BASIS_SITES[lattice] * int(np.prod(np.asarray(dims, dtype=np.int64))))
 

@@ -46,6 +46,11 @@ MUTANTS = [
     ("exchange ignores the round parity", "for (int i = (int)(round & 1u); i + 1 < R; i += 2)",
      "for (int i = 0; i + 1 < R; i += 2)",
      ["test_oracle_tempering.py::test_exchange_special_cases"]),
+    ("heat capacity without beta^2", "return beta * beta * v / (double)N;", "return v / (double)N;",
+     ["test_oracle_anneal.py::test_heat_capacity_closed_forms",
+      "test_oracle_anneal.py::test_heat_capacity_exact_sixteen_site_cell"]),
+    ("heat capacity from the sample variance", "v = v / (double)n;", "v = v / (double)(n - 1);",
+     ["test_oracle_anneal.py::test_heat_capacity_closed_forms"]),
 ]
 
 
