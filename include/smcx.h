@@ -247,6 +247,28 @@ int smcx_exchange(smcx_lattice *h, int32_t round, uint64_t seed, const double *b
                   double *E_dev, int64_t *xstats_dev, smcx_tie *ties_dev, int32_t tie_cap,
                   int32_t *tie_count_dev, void *stream);
 
+/* Stepwise anneal with energy recording (the paper's protocol: start hot,
+ * lower T in steps, discard sweeps at each temperature before measuring;
+ * Methods, MC simulation paragraph after Tab. 4).  Step s = 0 .. n_steps-1
+ * runs `warmup` sweeps, then `record` sweeps each followed by the energies
+ * of every replica, all at beta_steps_dev[s][r]; sweep indices run from
+ * first_sweep on, (warmup + record) per step.
+ *   beta_steps_dev [n_steps][R] binary64 (device).
+ *   counts_dev [R][S][K][K] int64: scratch, overwritten.
+ *   E_dev [n_steps][record][R] binary64: recorded energies (smcx_energy_dev).
+ *   cv_dev [n_steps][R] binary64: heat capacity per site in units of k_B,
+ *     beta^2 Var(E) / N_r over the step's recorded energies (two passes,
+ *     j ascending: m = sum E / n, v = sum (E - m)^2 / n, c = beta beta v / N).
+ *   stats_dev, ties_dev, tie_cap, tie_count_dev, mode: as for smcx_sweep.
+ * counts_dev, E_dev and cv_dev may be NULL when record == 0.  Everything is
+ * enqueued on `stream` without host synchronisation.  Errors:
+ * SMCX_E_INVALID_ARG (negative sizes, missing buffers, sweep index past
+ * 2^32), SMCX_E_NOT_READY before smcx_set_epi. */
+int smcx_anneal(smcx_lattice *h, int32_t n_steps, int32_t warmup, int32_t record, uint64_t seed,
+                uint32_t first_sweep, const double *beta_steps_dev, int64_t *counts_dev, double *E_dev,
+                double *cv_dev, int64_t *stats_dev, smcx_tie *ties_dev, int32_t tie_cap,
+                int32_t *tie_count_dev, int32_t mode, void *stream);
+
 /* Stateless batched pair counts for B configurations of one geometry:
  * occ_batch_dev device uint8 [B][N] (N = m * dims[0]*dims[1]*dims[2]),
  * counts_dev device int64 [B][S][K][K] (overwritten).  The gradient of

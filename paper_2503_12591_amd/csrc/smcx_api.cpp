@@ -766,8 +766,12 @@ static int check_sweep_args(smcx_lattice* h, const double* beta_dev, int64_t* st
 // tau_end) of each; beta_dev row js (R entries) belongs to sweep js.
 static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t first_sweep, int tau_begin,
                       int tau_end, const double* beta_dev, int64_t* stats_dev, smcx_tie* ties_dev, int32_t tie_cap,
-                      int32_t* tie_count_dev, int32_t mode, hipStream_t st, uint32_t* sweep_counter = nullptr)
+                      int32_t* tie_count_dev, int32_t mode, hipStream_t st, uint32_t* sweep_counter = nullptr,
+                      int64_t beta_row_stride = -1)
 {
+    // sweep js reads beta row js (R entries) by default; a stride of 0 gives
+    // every sweep of the call the same row
+    const int64_t bstride = beta_row_stride < 0 ? (int64_t)h->P.R : beta_row_stride;
     // with a device sweep counter (graph capture) the kernels read the sweep
     // index from it and first_sweep counts from 0
     if (sweep_counter) first_sweep = 0;
@@ -794,7 +798,7 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
     if (mode == SMCX_MODE_PERSISTENT) {
         a.first_sweep = first_sweep;
         a.beta = beta_dev;
-        a.beta_stride = P.R;
+        a.beta_stride = bstride;
         a.nb = P.group;
         if (int rc = timed_launch(h, h->k_persistent, dim3(P.R), P.block, P.lds.total, st, a)) return rc;
     } else if (rows) {
@@ -812,7 +816,7 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
         for (const Replica& R : P.reps) max_groups = std::max(max_groups, R.M[1] * R.M[2]);
         for (int js = 0; js < n_sweeps; ++js) {
             ra.first_sweep = first_sweep + (uint32_t)js;
-            ra.beta = beta_dev + (int64_t)js * P.R;
+            ra.beta = beta_dev + (int64_t)js * bstride;
             if (P.rows_mixed) {
                 for (int q = 0; q < max_groups; ++q) {
                     ra.gq = q;
@@ -833,7 +837,7 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
         const dim3 grid((unsigned)std::min<int64_t>(h->stream_wgs, 8 * ((P.total_tiles + 7) / 8)));
         for (int js = 0; js < n_sweeps; ++js) {
             a.first_sweep = first_sweep + (uint32_t)js;
-            a.beta = beta_dev + (int64_t)js * P.R;
+            a.beta = beta_dev + (int64_t)js * bstride;
             const int end = std::min(tau_end, P.max_nA);
             for (int g = tau_begin; g < end; g = group_end(g, end)) {
                 a.g = g;
@@ -844,7 +848,7 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
     } else {
         for (int js = 0; js < n_sweeps; ++js) {
             a.first_sweep = first_sweep + (uint32_t)js;
-            a.beta = beta_dev + (int64_t)js * P.R;
+            a.beta = beta_dev + (int64_t)js * bstride;
             for (int r = 0; r < P.R; ++r) {
                 a.only_rep = r;
                 const dim3 grid((unsigned)std::min<int64_t>(h->stream_wgs, 8 * ((P.reps[r].ntiles + 7) / 8)));
@@ -972,6 +976,38 @@ int smcx_exchange(smcx_lattice* h, int32_t round, uint64_t seed, const double* b
     if (int rc = smcx_energy_dev(h, counts_dev, E_dev, stream)) return rc;
     SMCX_HIP(launch_exchange(E_dev, beta_slot_dev, rep_at_dev, P.R, seed, (uint32_t)round, beta_dev, n_beta_rows,
                              xstats_dev, ties_dev, tie_cap, tie_count_dev, (hipStream_t)stream));
+    return SMCX_OK;
+}
+
+int smcx_anneal(smcx_lattice* h, int32_t n_steps, int32_t warmup, int32_t record, uint64_t seed, uint32_t first_sweep,
+                const double* beta_steps_dev, int64_t* counts_dev, double* E_dev, double* cv_dev, int64_t* stats_dev,
+                smcx_tie* ties_dev, int32_t tie_cap, int32_t* tie_count_dev, int32_t mode, void* stream)
+{
+    if (n_steps < 0 || warmup < 0 || record < 0) return fail(SMCX_E_INVALID_ARG, "n_steps, warmup and record must be >= 0");
+    if (int rc = check_sweep_args(h, beta_steps_dev, stats_dev, ties_dev, tie_cap, tie_count_dev, mode)) return rc;
+    if (record > 0 && (!counts_dev || !E_dev || !cv_dev))
+        return fail(SMCX_E_INVALID_ARG, "counts_dev, E_dev and cv_dev are required when record > 0");
+    const Plan& P = h->P;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t per = (int64_t)warmup + record;
+    if ((int64_t)first_sweep + per * n_steps > 0xffffffffLL) return fail(SMCX_E_INVALID_ARG, "sweep index overflows 32 bits");
+    for (int s = 0; s < n_steps; ++s) {
+        const double* b = beta_steps_dev + (int64_t)s * P.R;
+        const uint32_t t0 = first_sweep + (uint32_t)(s * per);
+        if (warmup > 0)
+            if (int rc = run_sweeps(h, warmup, seed, t0, 0, P.max_nA, b, stats_dev, ties_dev, tie_cap, tie_count_dev,
+                                    mode, st, nullptr, 0))
+                return rc;
+        for (int j = 0; j < record; ++j) {
+            if (int rc = run_sweeps(h, 1, seed, t0 + (uint32_t)(warmup + j), 0, P.max_nA, b, stats_dev, ties_dev,
+                                    tie_cap, tie_count_dev, mode, st, nullptr, 0))
+                return rc;
+            if (int rc = smcx_energy_dev(h, counts_dev, E_dev + ((int64_t)s * record + j) * P.R, stream)) return rc;
+        }
+    }
+    if (record > 0 && n_steps > 0)
+        SMCX_HIP(launch_heat_capacity(E_dev, beta_steps_dev, (const RepDev*)(h->ws + P.off_reps), n_steps, record, P.R,
+                                      cv_dev, st));
     return SMCX_OK;
 }
 

@@ -1649,6 +1649,40 @@ __global__ __launch_bounds__(kBlock) void k_exchange(const double* E, const doub
     }
 }
 
+// Heat capacity per site (units of k_B) of every (step, replica) from its
+// recorded energies E[s][j][r], j < n_rec: c = (beta beta) v / N with
+// m = (sum_j E) / n_rec and v = (sum_j (E - m)^2) / n_rec, j ascending in
+// binary64 (the canonical fluctuation formula); beta = beta_steps[s][r].
+__global__ void k_heat_capacity(const double* E, const double* beta_steps, const RepDev* reps, int n_steps,
+                                int n_rec, int R, double* cv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_steps * R) return;
+    const int64_t s = i / R;
+    const int r = (int)(i - s * R);
+    const double* e = E + s * n_rec * R + r;
+    double m = 0.0;
+    for (int j = 0; j < n_rec; ++j) m = m + e[(int64_t)j * R];
+    m = m / (double)n_rec;
+    double v = 0.0;
+    for (int j = 0; j < n_rec; ++j) {
+        const double d = e[(int64_t)j * R] - m;
+        v = v + d * d;
+    }
+    v = v / (double)n_rec;
+    const double b = beta_steps[i];
+    cv[i] = b * b * v / (double)reps[r].N;
+}
+
+hipError_t launch_heat_capacity(const double* E, const double* beta_steps, const RepDev* reps, int n_steps, int n_rec,
+                                int R, double* cv, hipStream_t st)
+{
+    const int64_t n = (int64_t)n_steps * R;
+    hipLaunchKernelGGL(k_heat_capacity, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, E, beta_steps,
+                       reps, n_steps, n_rec, R, cv);
+    return hipGetLastError();
+}
+
 hipError_t launch_energy(const int64_t* C, const double* V, int R, int SKK, double* E, hipStream_t st)
 {
     hipLaunchKernelGGL(k_energy, dim3((unsigned)((R + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, C, V, R, SKK, E);

@@ -29,7 +29,7 @@ EXPORTS = [
     "smcx_pair_counts", "smcx_energy", "smcx_sro", "smcx_energy_backward", "smcx_ladder_capture",
     "smcx_sweep_capture",
     "smcx_graph_launch", "smcx_graph_destroy", "smcx_timing_enable", "smcx_timing_read",
-    "smcx_energy_dev", "smcx_exchange",
+    "smcx_energy_dev", "smcx_exchange", "smcx_anneal",
 ]
 
 
@@ -79,6 +79,7 @@ def lib():
     L.smcx_timing_read.argtypes = [p, p, p]
     L.smcx_energy_dev.argtypes = [p, p, p, p]
     L.smcx_exchange.argtypes = [p, i32, u64, p, p, p, i32, p, p, p, p, i32, p, p]
+    L.smcx_anneal.argtypes = [p, i32, i32, i32, u64, u32, p, p, p, p, p, p, i32, p, i32, p]
     _lib = L
     return L
 
@@ -273,6 +274,30 @@ class Lattice:
             E = self.torch.zeros(self.R, dtype=self.torch.float64, device="cuda")
         _check(lib().smcx_energy_dev(self.h, _ptr(self.counts), _ptr(E), _stream(self.torch)))
         return E
+
+    def anneal(self, beta_steps, warmup: int, record: int, seed: int, first_sweep: int = 0, mode="auto",
+               tie_cap: int = 4096, stats=None, ties=None, tie_count=None):
+        """Stepwise anneal (smcx_anneal): beta_steps [n_steps] or [n_steps][R].
+        Returns dict of CUDA tensors E [n_steps][record][R], cv [n_steps][R]
+        (heat capacity per site in units of k_B), stats, ties, tie_count."""
+        torch = self.torch
+        b = np.asarray(beta_steps, np.float64)
+        n_steps = b.shape[0]
+        b = torch.from_numpy(np.array(np.broadcast_to(b.reshape(n_steps, -1), (n_steps, self.R)))).cuda()
+        E = torch.zeros((n_steps, max(record, 1), self.R), dtype=torch.float64, device="cuda")
+        cv = torch.zeros((n_steps, self.R), dtype=torch.float64, device="cuda")
+        if stats is None:
+            stats = torch.zeros(self.R * 3, dtype=torch.int64, device="cuda")
+        if ties is None:
+            ties = torch.zeros(max(tie_cap, 1) * TIE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        if tie_count is None:
+            tie_count = torch.zeros(1, dtype=torch.int32, device="cuda")
+        mode = MODES[mode] if isinstance(mode, str) else int(mode)
+        _check(lib().smcx_anneal(self.h, n_steps, warmup, record, C.c_uint64(seed), C.c_uint32(first_sweep),
+                                 _ptr(b), _ptr(self.counts), _ptr(E), _ptr(cv), _ptr(stats), _ptr(ties), tie_cap,
+                                 _ptr(tie_count), mode, _stream(torch)))
+        self._last_beta = b
+        return dict(E=E[:, :record], cv=cv, stats=stats, ties=ties, tie_count=tie_count)
 
     def sro(self) -> np.ndarray:
         a = np.zeros((self.R, self.S, self.K, self.K), np.float64)
