@@ -225,6 +225,8 @@ def main():
         out["ladder"] = ladder_bench(args)
         print("[bench] tempering", file=sys.stderr, flush=True)
         out["tempering"] = tempering_bench(args)
+        print("[bench] anneal", file=sys.stderr, flush=True)
+        out["anneal"] = anneal_bench(args)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(lattice, dims, K, S, cells, occ_host, V, seed, beta,
@@ -358,6 +360,46 @@ def tempering_bench(args, rounds: int = 4, sweeps_per_round: int = 5):
             "sweeps_per_round": sweeps_per_round, "unit": "attempted swaps/s",
             "swaps_per_s": rounds * sweeps_per_round * N / secs, "exchange_round_us": ex * 1e6,
             "trade_fraction": float(x0[1] / max(x0[0], 1))}
+
+
+def anneal_bench(args, warmup: int = 5, record: int = 5):
+    """Stepwise anneal of the BCC 64^3 lattice (4 species, 4 shells) from
+    2000 K down to 300 K in 50 K steps, `warmup` sweeps then `record` sweeps
+    with energies per temperature and the heat capacity of every step
+    (smcx_anneal): attempted swaps/s of the whole protocol and the time of the
+    same sweeps in one call without recording (the difference is the cost of
+    the energy records).  A throughput measurement: with a few sweeps per
+    temperature the heat capacities are not equilibrium values."""
+    import torch
+    from paper_2503_12591_amd import inputs as I
+    from paper_2503_12591_amd import smcx
+    wl = I.c2_anneal_bcc()
+    T = I.stepwise_temperatures(2000.0, 300.0, 50.0)
+    beta = I.beta_of_T(T)
+    occ = torch.from_numpy(wl.occ()).cuda()
+    lat = smcx.Lattice(wl.lattice, wl.dims, wl.K, wl.S, occ, ell=4)
+    lat.set_epi(wl.V)
+    lat.anneal(beta[:1], 1, 1, seed=0, mode="stream")  # warm-up
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3, r
+
+    per = warmup + record
+    secs, out = timed(lambda: lat.anneal(beta, warmup, record, seed=0, first_sweep=2, mode="stream"))
+    bt = np.repeat(beta, per).reshape(-1, 1)
+    plain, _ = timed(lambda: lat.sweep(len(bt), 0, bt, first_sweep=2 + len(bt), mode="stream"))
+    lat.close()
+    n_sweeps = len(T) * per
+    return {"workload": "bcc64_k4_s4_anneal2000to300_step50", "sites": wl.N, "temperatures": len(T),
+            "warmup": warmup, "record": record, "unit": "attempted swaps/s",
+            "swaps_per_s": n_sweeps * wl.N / secs, "ms": secs * 1e3,
+            "sweeps_only_ms": plain * 1e3, "records": len(T) * record}
 
 
 def algorithmic_bytes_per_launch(cells, N, m, launches_per_sweep):
