@@ -526,9 +526,11 @@ int pack_all(smcx_lattice* h, bool unpack, bool planar, hipStream_t st)
 {
     const Plan& P = h->P;
     for (int r = 0; r < P.R; ++r) {
-        const int64_t ncell = P.reps[r].N / P.m;
+        const Replica& R = P.reps[r];
+        // natural rows to unpack, padded rows (halo rows included) to pack
+        const int64_t nrows = unpack ? (int64_t)R.L[1] * R.L[2] : (int64_t)R.prows * (R.L[2] + 2 * kHalo);
         SMCX_HIP(launch_pack(P.lattice, P.K, unpack, planar, h->occ, h->ws, (const RepDev*)(h->ws + P.off_reps), r,
-                             ncell, st));
+                             nrows, st));
     }
     return SMCX_OK;
 }

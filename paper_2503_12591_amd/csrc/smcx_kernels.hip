@@ -1193,42 +1193,63 @@ __global__ void k_advance_counter(uint32_t* counter, uint32_t n)
     if (blockIdx.x == 0 && threadIdx.x == 0) *counter += n;
 }
 
-// Natural layout -> padded copy (all halo images).
+// Natural layout -> padded copy.  A workgroup fills whole padded rows
+// (halo rows and columns included: each padded row is the natural row at the
+// wrapped y, z, each byte the site at the wrapped x), a thread one dword of
+// the row at a time; bytes past a column's L0 + 2H sites stay 0.
 template <int M, bool PLANAR>
 __global__ void k_pack(const uint8_t* occ, uint8_t* ws, const RepDev* reps, int r, int F)
 {
     const RepDev& rep = reps[r];
     uint8_t* pad = ws + rep.pad_off;
     const uint8_t* o = occ + rep.occ_off;
-    const int64_t ncell = (int64_t)rep.L[0] * rep.L[1] * rep.L[2];
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(c % rep.L[0]);
-        const int64_t cr = c / rep.L[0];
-        const int y = (int)(cr % rep.L[1]);
-        const int z = (int)(cr / rep.L[1]);
+    const int L0 = rep.L[0], L1 = rep.L[1], L2 = rep.L[2];
+    const int pitch = PLANAR ? rep.prowp : rep.prow;
+    const int nrow = rep.prows * (L2 + 2 * kHalo);
+    const int words = pitch >> 2;
+    for (int row = blockIdx.x; row < nrow; row += gridDim.x) {
+        const int yp = row % rep.prows, zp = row / rep.prows;
+        int y = yp - kHalo, z = zp - kHalo;
+        y += y < 0 ? L1 : (y >= L1 ? -L1 : 0);
+        z += z < 0 ? L2 : (z >= L2 ? -L2 : 0);
+        const uint8_t* src = o + (int64_t)M * L0 * (y + (int64_t)L1 * z);
+        uint32_t* dst = (uint32_t*)(pad + (int64_t)row * pitch);
+        for (int w = threadIdx.x; w < words; w += blockDim.x) {
+            uint32_t v = 0;
 #pragma unroll
-        for (int b = 0; b < M; ++b) store_site<PLANAR>(pad, rep, M, x, y, z, b, (uint8_t)(o[M * c + b] * F));
+            for (int i = 0; i < 4; ++i) {
+                const int j = 4 * w + i;
+                const int b = PLANAR ? j / rep.cp : j % M;
+                int x = (PLANAR ? j - b * rep.cp : j / M) - kHalo;
+                if (b < M && x < L0 + kHalo) {
+                    x += x < 0 ? L0 : (x >= L0 ? -L0 : 0);
+                    v |= (uint32_t)(src[M * x + b] * F) << (8 * i);
+                }
+            }
+            dst[w] = v;
+        }
     }
 }
 
-// Padded copy interior -> natural layout.
+// Padded copy interior -> natural layout: a workgroup per natural row, a
+// thread per site byte.
 template <int M, bool PLANAR>
 __global__ void k_unpack(uint8_t* occ, const uint8_t* ws, const RepDev* reps, int r, int F)
 {
     const RepDev& rep = reps[r];
     const uint8_t* pad = ws + rep.pad_off;
     uint8_t* o = occ + rep.occ_off;
-    const int64_t ncell = (int64_t)rep.L[0] * rep.L[1] * rep.L[2];
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(c % rep.L[0]);
-        const int64_t cr = c / rep.L[0];
-        const int y = (int)(cr % rep.L[1]);
-        const int z = (int)(cr / rep.L[1]);
-        const uint8_t* row = pad + ((int64_t)(z + kHalo) * rep.prows + (y + kHalo)) * (PLANAR ? rep.prowp : rep.prow);
-#pragma unroll
-        for (int b = 0; b < M; ++b) o[M * c + b] = (uint8_t)species_of(row[row_byte<PLANAR>(rep, M, x, b)], F);
+    const int L0 = rep.L[0], L1 = rep.L[1], L2 = rep.L[2];
+    const int pitch = PLANAR ? rep.prowp : rep.prow;
+    const int n = M * L0;
+    for (int row = blockIdx.x; row < L1 * L2; row += gridDim.x) {
+        const int y = row % L1, z = row / L1;
+        const uint8_t* src = pad + ((int64_t)(z + kHalo) * rep.prows + (y + kHalo)) * pitch;
+        uint8_t* dst = o + (int64_t)n * row;
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            const int x = j / M, b = j - x * M;
+            dst[j] = (uint8_t)species_of(src[row_byte<PLANAR>(rep, M, x, b)], F);
+        }
     }
 }
 
@@ -1541,9 +1562,10 @@ hipError_t sweep_occupancy(const void* kernel, int block, size_t lds, int* block
 }
 
 hipError_t launch_pack(int lattice, int K, bool unpack, bool planar, uint8_t* occ, uint8_t* ws,
-                       const RepDev* reps, int r, int64_t ncell, hipStream_t st)
+                       const RepDev* reps, int r, int64_t nrows, hipStream_t st)
 {
-    int64_t nb = (ncell + kBlock - 1) / kBlock;
+    // a workgroup per row (padded rows to pack, natural rows to unpack)
+    int64_t nb = nrows;
     if (nb > 65536) nb = 65536;
     if (nb < 1) nb = 1;
     const dim3 g((unsigned)nb), b(kBlock);
