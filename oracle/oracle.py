@@ -78,6 +78,8 @@ def lib():
         L.or_exchange.argtypes = [C.c_int, p, p, p, u64, u32, p, i32, p, p, i32, p]
         L.or_heat_capacity.argtypes = [C.c_int, p, dbl, i64]
         L.or_heat_capacity.restype = dbl
+        L.or_local_energy.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, p]
+        L.or_clusters.argtypes = [C.c_int, p, p, dbl, p, p, p, p]
         _lib = L
     return _lib
 
@@ -341,3 +343,28 @@ def anneal(lattice, dims, K, S, cells, occ: np.ndarray, V, seed: int, beta_steps
             cv[s] = heat_capacity(E[s], b, N)
     return dict(E=E, cv=cv, stats=stats,
                 ties=np.concatenate(ties) if ties else np.zeros(0, TIE_DTYPE))
+
+
+def local_energy(lattice, dims, K, S, occ, V) -> np.ndarray:
+    """Per-site local energies (``or_local_energy``)."""
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    e = np.zeros(len(occ), np.float64)
+    if lib().or_local_energy(lattice, _ptr(_dims(dims)), K, S, _ptr(occ), _ptr(V), _ptr(e)) != 0:
+        raise ValueError("or_local_energy failed")
+    return e
+
+
+def clusters(lattice, dims, e, threshold: float):
+    """Clusters of sites with e <= threshold (``or_clusters``): returns
+    (label int32 [N], size int32 [N], n_clusters)."""
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    N = len(e)
+    label = np.zeros(N, np.int32)
+    size = np.zeros(N, np.int32)
+    nc = np.zeros(1, np.int64)
+    stack = np.zeros(max(N, 1), np.int64)
+    if lib().or_clusters(lattice, _ptr(_dims(dims)), _ptr(e), float(threshold), _ptr(label), _ptr(size),
+                         _ptr(nc), _ptr(stack)) != 0:
+        raise ValueError("or_clusters failed")
+    return label, size, int(nc[0])

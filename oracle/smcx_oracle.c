@@ -799,3 +799,83 @@ double or_heat_capacity(int n, const double *E, double beta, int64_t N)
     v = v / (double)n;
     return beta * beta * v / (double)N;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Local energies and clusters                                               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Local energy of every site, e_i = 1/2 sum_s sum_t n_i[s][t] V_s[sigma_i][t]
+ * with n_i[s][t] the number of shell-s neighbours of i with species t
+ * (periodic images counted with multiplicity), accumulated s, t ascending in
+ * binary64.  The half makes the local energies add up to E (Eq. Linear_EPI
+ * gives the per-site form; the paper computes local energies to find its
+ * nanostructures, Methods after Tab. 4).
+ */
+int or_local_energy(int lattice, const int32_t L[3], int K, int S, const uint8_t *occ, const double *V,
+                    double *e)
+{
+    or_sys sy;
+    if (sys_init(&sy, lattice, L, K, S) != OR_OK) return OR_EARG;
+    for (int64_t i = 0; i < sy.N; ++i) {
+        if (occ[i] >= K) return OR_EARG;
+        int h[3];
+        site_pos(&sy, i, h);
+        int n[OR_MAXS][OR_MAXK];
+        memset(n, 0, sizeof(n));
+        for (int s = 0; s < S; ++s)
+            for (int k = 0; k < sy.Z[s]; ++k) n[s][occ[site_at(&sy, h, sy.d[s][k])]] += 1;
+        double acc = 0.0;
+        for (int s = 0; s < S; ++s)
+            for (int t = 0; t < K; ++t) acc = acc + (double)n[s][t] * V[((size_t)s * K + occ[i]) * K + t];
+        e[i] = 0.5 * acc;
+    }
+    return OR_OK;
+}
+
+/*
+ * Clusters of low-energy sites (the paper's union-find step, Methods after
+ * Tab. 4): site i is marked when e[i] <= threshold; marked nearest neighbours
+ * (shell 1, periodic) belong to the same cluster.  label[i] is the smallest
+ * site index of i's cluster, or -1 for an unmarked site; size[i] is the
+ * number of sites of the cluster whose smallest index is i, else 0.  Found by
+ * a flood fill from each unlabelled marked site in index order (the first
+ * site reached is the smallest of its cluster).  *n_clusters counts them.
+ * `stack` is caller scratch of N entries.
+ */
+int or_clusters(int lattice, const int32_t L[3], const double *e, double threshold, int32_t *label, int32_t *size,
+                int64_t *n_clusters, int64_t *stack)
+{
+    or_sys sy;
+    if (sys_init(&sy, lattice, L, 2, 1) != OR_OK) return OR_EARG;
+    if (sy.N > 0x7fffffffLL) return OR_EARG;
+    for (int64_t i = 0; i < sy.N; ++i) {
+        label[i] = -1;
+        size[i] = 0;
+    }
+    int64_t nc = 0;
+    for (int64_t i = 0; i < sy.N; ++i) {
+        if (!(e[i] <= threshold) || label[i] >= 0) continue;
+        int64_t top = 0;
+        stack[top++] = i;
+        label[i] = (int32_t)i;
+        int32_t count = 0;
+        while (top > 0) {
+            int64_t a = stack[--top];
+            ++count;
+            int h[3];
+            site_pos(&sy, a, h);
+            for (int k = 0; k < sy.Z[0]; ++k) {
+                int64_t j = site_at(&sy, h, sy.d[0][k]);
+                if (e[j] <= threshold && label[j] < 0) {
+                    label[j] = (int32_t)i;
+                    stack[top++] = j;
+                }
+            }
+        }
+        size[i] = count;
+        ++nc;
+    }
+    *n_clusters = nc;
+    return OR_OK;
+}
