@@ -264,6 +264,29 @@ int smcx_exchange(smcx_lattice *h, int32_t round, uint64_t seed, const double *b
  * enqueued on `stream` without host synchronisation.  Errors:
  * SMCX_E_INVALID_ARG (negative sizes, missing buffers, sweep index past
  * 2^32), SMCX_E_NOT_READY before smcx_set_epi. */
+/* Local energy of every site of one replica: e_dev [N_r] binary64 receives
+ * e_i = 1/2 sum_s sum_t n_i[s][t] V_s[sigma_i][t] (n_i[s][t]: shell-s
+ * neighbours of species t, periodic images with multiplicity; s, t
+ * ascending), so that sum_i e_i = E.  The per-site form of Eq. Linear_EPI;
+ * the paper computes it to find nanostructures (Methods after Tab. 4).
+ * Asynchronous.  Errors: SMCX_E_INVALID_ARG (replica out of range, NULL),
+ * SMCX_E_UNSUPPORTED for N_r >= 2^31, SMCX_E_NOT_READY before smcx_set_epi. */
+int smcx_local_energy(smcx_lattice *h, int32_t replica, double *e_dev, void *stream);
+
+/* Clusters of low-energy sites (the paper's union-find step, Methods after
+ * Tab. 4): site i of the replica is marked when e_dev[i] <= threshold, and
+ * marked nearest neighbours (shell 1, periodic) join one cluster.
+ *   label_dev [N_r] int32, written: the smallest site index of i's cluster,
+ *     or -1 for an unmarked site (unique, whatever the order of unions).
+ *   size_dev [N_r] int32, written: the number of sites of the cluster whose
+ *     smallest site is i, else 0.
+ *   n_clusters_dev [1] int64, written: the number of clusters.
+ * Device memory owned by the caller; asynchronous, no allocation.  Errors:
+ * SMCX_E_INVALID_ARG (replica out of range, NULL), SMCX_E_UNSUPPORTED for
+ * N_r >= 2^31. */
+int smcx_clusters(smcx_lattice *h, int32_t replica, const double *e_dev, double threshold,
+                  int32_t *label_dev, int32_t *size_dev, int64_t *n_clusters_dev, void *stream);
+
 int smcx_anneal(smcx_lattice *h, int32_t n_steps, int32_t warmup, int32_t record, uint64_t seed,
                 uint32_t first_sweep, const double *beta_steps_dev, int64_t *counts_dev, double *E_dev,
                 double *cv_dev, int64_t *stats_dev, smcx_tie *ties_dev, int32_t tie_cap,

@@ -80,6 +80,7 @@ def lib():
         L.or_heat_capacity.restype = dbl
         L.or_local_energy.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, p]
         L.or_clusters.argtypes = [C.c_int, p, p, dbl, p, p, p, p]
+        L.or_local_energy_at.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, p, i64, p]
         _lib = L
     return _lib
 
@@ -352,6 +353,18 @@ def local_energy(lattice, dims, K, S, occ, V) -> np.ndarray:
     e = np.zeros(len(occ), np.float64)
     if lib().or_local_energy(lattice, _ptr(_dims(dims)), K, S, _ptr(occ), _ptr(V), _ptr(e)) != 0:
         raise ValueError("or_local_energy failed")
+    return e
+
+
+def local_energy_at(lattice, dims, K, S, occ, V, idx) -> np.ndarray:
+    """Local energies of the listed sites only (``or_local_energy_at``)."""
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    e = np.zeros(len(idx), np.float64)
+    if lib().or_local_energy_at(lattice, _ptr(_dims(dims)), K, S, _ptr(occ), _ptr(V), _ptr(idx), len(idx),
+                                _ptr(e)) != 0:
+        raise ValueError("or_local_energy_at failed")
     return e
 
 

@@ -812,23 +812,42 @@ double or_heat_capacity(int n, const double *E, double beta, int64_t N)
  * gives the per-site form; the paper computes local energies to find its
  * nanostructures, Methods after Tab. 4).
  */
+static double local_energy_site(const or_sys *sy, const uint8_t *occ, const double *V, int64_t i)
+{
+    int K = sy->K, S = sy->S;
+    int h[3];
+    site_pos(sy, i, h);
+    int n[OR_MAXS][OR_MAXK];
+    memset(n, 0, sizeof(n));
+    for (int s = 0; s < S; ++s)
+        for (int k = 0; k < sy->Z[s]; ++k) n[s][occ[site_at(sy, h, sy->d[s][k])]] += 1;
+    double acc = 0.0;
+    for (int s = 0; s < S; ++s)
+        for (int t = 0; t < K; ++t) acc = acc + (double)n[s][t] * V[((size_t)s * K + occ[i]) * K + t];
+    return acc * 0.5;
+}
+
 int or_local_energy(int lattice, const int32_t L[3], int K, int S, const uint8_t *occ, const double *V,
                     double *e)
 {
     or_sys sy;
     if (sys_init(&sy, lattice, L, K, S) != OR_OK) return OR_EARG;
-    for (int64_t i = 0; i < sy.N; ++i) {
+    for (int64_t i = 0; i < sy.N; ++i)
         if (occ[i] >= K) return OR_EARG;
-        int h[3];
-        site_pos(&sy, i, h);
-        int n[OR_MAXS][OR_MAXK];
-        memset(n, 0, sizeof(n));
-        for (int s = 0; s < S; ++s)
-            for (int k = 0; k < sy.Z[s]; ++k) n[s][occ[site_at(&sy, h, sy.d[s][k])]] += 1;
-        double acc = 0.0;
-        for (int s = 0; s < S; ++s)
-            for (int t = 0; t < K; ++t) acc = acc + (double)n[s][t] * V[((size_t)s * K + occ[i]) * K + t];
-        e[i] = 0.5 * acc;
+    for (int64_t i = 0; i < sy.N; ++i) e[i] = local_energy_site(&sy, occ, V, i);
+    return OR_OK;
+}
+
+/* The same for the n listed sites only (e[j] for site idx[j]); occupancy
+ * values are not checked. */
+int or_local_energy_at(int lattice, const int32_t L[3], int K, int S, const uint8_t *occ, const double *V,
+                       const int64_t *idx, int64_t n, double *e)
+{
+    or_sys sy;
+    if (sys_init(&sy, lattice, L, K, S) != OR_OK) return OR_EARG;
+    for (int64_t j = 0; j < n; ++j) {
+        if (idx[j] < 0 || idx[j] >= sy.N) return OR_EARG;
+        e[j] = local_energy_site(&sy, occ, V, idx[j]);
     }
     return OR_OK;
 }

@@ -1013,6 +1013,34 @@ int smcx_anneal(smcx_lattice* h, int32_t n_steps, int32_t warmup, int32_t record
     return SMCX_OK;
 }
 
+int smcx_local_energy(smcx_lattice* h, int32_t replica, double* e_dev, void* stream)
+{
+    if (int rc = check_handle(h)) return rc;
+    if (!h->epi_set) return fail(SMCX_E_NOT_READY, "smcx_set_epi has not been called");
+    const Plan& P = h->P;
+    if (replica < 0 || replica >= P.R) return fail(SMCX_E_INVALID_ARG, "replica out of range");
+    if (!e_dev) return fail(SMCX_E_INVALID_ARG, "e_dev is NULL");
+    const Replica& R = P.reps[replica];
+    if (R.N > 0x7fffffffLL) return fail(SMCX_E_UNSUPPORTED, "local energies need fewer than 2^31 sites per replica");
+    SMCX_HIP(launch_local_energy(P.lattice, h->occ + R.occ_off, R.L, P.K, P.S, (const double*)(h->ws + P.off_V), e_dev,
+                                 (hipStream_t)stream));
+    return SMCX_OK;
+}
+
+int smcx_clusters(smcx_lattice* h, int32_t replica, const double* e_dev, double threshold, int32_t* label_dev,
+                  int32_t* size_dev, int64_t* n_clusters_dev, void* stream)
+{
+    if (int rc = check_handle(h)) return rc;
+    const Plan& P = h->P;
+    if (replica < 0 || replica >= P.R) return fail(SMCX_E_INVALID_ARG, "replica out of range");
+    if (!e_dev || !label_dev || !size_dev || !n_clusters_dev)
+        return fail(SMCX_E_INVALID_ARG, "e_dev, label_dev, size_dev and n_clusters_dev are required");
+    const Replica& R = P.reps[replica];
+    if (R.N > 0x7fffffffLL) return fail(SMCX_E_UNSUPPORTED, "clusters need fewer than 2^31 sites per replica");
+    SMCX_HIP(launch_clusters(P.lattice, e_dev, R.L, threshold, label_dev, size_dev, n_clusters_dev, (hipStream_t)stream));
+    return SMCX_OK;
+}
+
 int smcx_sro(smcx_lattice* h, int64_t* counts_dev, double* alpha_host, void* stream)
 {
     if (int rc = check_handle(h)) return rc;

@@ -1705,6 +1705,207 @@ hipError_t launch_heat_capacity(const double* E, const double* beta_steps, const
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Local energies and clusters of low-energy sites.
+//
+// k_local_energy: e_i = 1/2 sum_s sum_t n_i[s][t] V_s[sigma_i][t] (s, t
+// ascending, binary64), n_i[s][t] counted from the natural layout with the
+// periodic wrap.  A thread takes a conventional cell and each of its basis
+// sites in turn, so every neighbour displacement is a compile-time constant.
+//
+// Clusters: site i is marked when e_i <= threshold; marked nearest neighbours
+// join.  parent[] starts as i (marked) or -1, and always points at a smaller
+// or equal index: a union hooks the larger of two roots under the smaller
+// (compare-and-swap), a find halves the path to an ancestor.  The smallest
+// site of a cluster is therefore its final root, whatever the order of the
+// unions.  Every access to parent[] is an agent-scope atomic (the L2 of one
+// XCD does not see another's plain stores); a failed hook continues from the
+// value the swap returned, and a find only descends, so both loops end.
+// ---------------------------------------------------------------------------
+template <int LAT, int B>
+__device__ __forceinline__ double local_energy_at(const uint8_t* occ, int x, int y, int z, int L0, int L1, int L2,
+                                                  int K, int S, const double* Vs)
+{
+    constexpr Geometry G = kGeom[LAT];
+    constexpr int m = G.m;
+    uint64_t acc[kMaxShells];
+#pragma unroll
+    for (int s = 0; s < kMaxShells; ++s) {
+        uint64_t a = 0;
+        if (s < S) {
+#pragma unroll
+            for (int n = 0; n < G.Z[s]; ++n) {
+                const Nb nb = nb_of(G, B, G.v[s][n][0], G.v[s][n][1], G.v[s][n][2]);
+                int xx = x + nb.dx, yy = y + nb.dy, zz = z + nb.dz;
+                xx += xx < 0 ? L0 : (xx >= L0 ? -L0 : 0);
+                yy += yy < 0 ? L1 : (yy >= L1 ? -L1 : 0);
+                zz += zz < 0 ? L2 : (zz >= L2 ? -L2 : 0);
+                const uint32_t t = occ[nb.bt + m * (xx + L0 * (yy + L1 * zz))] & 7u;  // species < K <= 8
+                a += (uint64_t)1 << (8 * t);
+            }
+        }
+        acc[s] = a;
+    }
+    const int p = min((int)occ[B + m * (x + L0 * (y + L1 * z))], K - 1);  // checked < K at init
+    double e = 0.0;
+#pragma unroll
+    for (int s = 0; s < kMaxShells; ++s)
+        if (s < S)
+            for (int t = 0; t < K; ++t)
+                e = e + (double)(int)((acc[s] >> (8 * t)) & 0xff) * Vs[(s * K + p) * K + t];
+    return 0.5 * e;
+}
+
+template <int LAT, int B>
+__device__ __forceinline__ void local_energy_sites(const uint8_t* occ, int c, int L0, int L1, int L2, int K, int S,
+                                                   const double* Vs, double* e)
+{
+    constexpr int m = kGeom[LAT].m;
+    if constexpr (B < m) {
+        const int x = c % L0, cr = c / L0, y = cr % L1, z = cr / L1;
+        e[B + m * c] = local_energy_at<LAT, B>(occ, x, y, z, L0, L1, L2, K, S, Vs);
+        local_energy_sites<LAT, B + 1>(occ, c, L0, L1, L2, K, S, Vs, e);
+    }
+}
+
+template <int LAT>
+__global__ __launch_bounds__(kBlock) void k_local_energy(const uint8_t* occ, int L0, int L1, int L2, int K, int S,
+                                                         const double* V, double* e)
+{
+    __shared__ double Vs[kMaxShells * kMaxK * kMaxK];
+    for (int i = threadIdx.x; i < S * K * K; i += blockDim.x) Vs[i] = V[i];
+    __syncthreads();
+    const int ncell = L0 * L1 * L2;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x)
+        local_energy_sites<LAT, 0>(occ, c, L0, L1, L2, K, S, Vs, e);
+}
+
+__device__ __forceinline__ int32_t par_load(const int32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void par_store(int32_t* p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x.  HALVE: point x at its grandparent on the way (while trees
+// still merge any ancestor will do); without it the walk only reads, as the
+// final labelling needs: there a halving store racing with the owner's
+// store of the root could leave an older ancestor as the label.
+template <bool HALVE>
+__device__ __forceinline__ int32_t cluster_find(int32_t* parent, int32_t x)
+{
+    while (true) {
+        const int32_t p = par_load(parent + x);
+        if (p == x) return x;
+        const int32_t gp = par_load(parent + p);
+        if (HALVE && gp != p) par_store(parent + x, gp);  // gp is an ancestor of x
+        x = gp;
+    }
+}
+
+__global__ void k_cluster_init(const double* e, int N, double threshold, int32_t* parent, int32_t* size)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        parent[i] = e[i] <= threshold ? i : -1;
+        size[i] = 0;
+    }
+}
+
+template <int LAT, int B>
+__device__ __forceinline__ void cluster_hook_site(int32_t* parent, int c, int L0, int L1, int L2)
+{
+    constexpr Geometry G = kGeom[LAT];
+    constexpr int m = G.m;
+    if constexpr (B < m) {
+        const int i = B + m * c;
+        if (par_load(parent + i) >= 0) {
+            const int x = c % L0, cr = c / L0, y = cr % L1, z = cr / L1;
+#pragma unroll
+            for (int n = 0; n < G.Z[0]; ++n) {
+                const Nb nb = nb_of(G, B, G.v[0][n][0], G.v[0][n][1], G.v[0][n][2]);
+                int xx = x + nb.dx, yy = y + nb.dy, zz = z + nb.dz;
+                xx += xx < 0 ? L0 : (xx >= L0 ? -L0 : 0);
+                yy += yy < 0 ? L1 : (yy >= L1 ? -L1 : 0);
+                zz += zz < 0 ? L2 : (zz >= L2 ? -L2 : 0);
+                const int j = nb.bt + m * (xx + L0 * (yy + L1 * zz));
+                if (j <= i || par_load(parent + j) < 0) continue;  // each marked pair once
+                int a = i, b = j;
+                while (true) {
+                    a = cluster_find<true>(parent, a);
+                    b = cluster_find<true>(parent, b);
+                    if (a == b) break;
+                    if (a < b) {
+                        const int t = a;
+                        a = b;
+                        b = t;
+                    }
+                    int expected = a;  // hook root a under the smaller root b
+                    if (__hip_atomic_compare_exchange_strong(parent + a, &expected, b, __ATOMIC_RELAXED,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                        break;
+                    a = expected;  // a was no longer a root: go on from its parent (< a)
+                }
+            }
+        }
+        cluster_hook_site<LAT, B + 1>(parent, c, L0, L1, L2);
+    }
+}
+
+template <int LAT>
+__global__ void k_cluster_hook(int32_t* parent, int L0, int L1, int L2)
+{
+    const int ncell = L0 * L1 * L2;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x)
+        cluster_hook_site<LAT, 0>(parent, c, L0, L1, L2);
+}
+
+__global__ void k_cluster_flatten(int32_t* parent, int N, int32_t* size, int64_t* n_clusters)
+{
+    int roots = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        if (par_load(parent + i) < 0) continue;
+        const int32_t r = cluster_find<false>(parent, i);  // the trees are final; only site i's own entry is written
+        par_store(parent + i, r);
+        atomicAdd(size + r, 1);
+        roots += r == i;
+    }
+    const int w = wave_sum_i(roots);
+    if ((threadIdx.x & 63) == 0 && w) atomicAdd((unsigned long long*)n_clusters, (unsigned long long)w);
+}
+
+hipError_t launch_local_energy(int lattice, const uint8_t* occ, const int32_t* L, int K, int S, const double* V,
+                               double* e, hipStream_t st)
+{
+    const int64_t ncell = (int64_t)L[0] * L[1] * L[2];
+    const unsigned nb = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (ncell + kBlock - 1) / kBlock), 1 << 20);
+    if (lattice == SMCX_BCC)
+        hipLaunchKernelGGL(k_local_energy<SMCX_BCC>, dim3(nb), dim3(kBlock), 0, st, occ, L[0], L[1], L[2], K, S, V, e);
+    else
+        hipLaunchKernelGGL(k_local_energy<SMCX_FCC>, dim3(nb), dim3(kBlock), 0, st, occ, L[0], L[1], L[2], K, S, V, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_clusters(int lattice, const double* e, const int32_t* L, double threshold, int32_t* label,
+                           int32_t* size, int64_t* n_clusters, hipStream_t st)
+{
+    const int m = lattice == SMCX_BCC ? 2 : 4;
+    const int64_t ncell = (int64_t)L[0] * L[1] * L[2];
+    const int N = (int)(m * ncell);
+    const unsigned nbs = (unsigned)std::min<int64_t>(std::max<int64_t>(1, ((int64_t)N + kBlock - 1) / kBlock), 1 << 20);
+    const unsigned nbc = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (ncell + kBlock - 1) / kBlock), 1 << 20);
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(kBlock), 0, st, n_clusters, (int64_t)1, (int64_t)0);
+    hipLaunchKernelGGL(k_cluster_init, dim3(nbs), dim3(kBlock), 0, st, e, N, threshold, label, size);
+    if (lattice == SMCX_BCC)
+        hipLaunchKernelGGL(k_cluster_hook<SMCX_BCC>, dim3(nbc), dim3(kBlock), 0, st, label, L[0], L[1], L[2]);
+    else
+        hipLaunchKernelGGL(k_cluster_hook<SMCX_FCC>, dim3(nbc), dim3(kBlock), 0, st, label, L[0], L[1], L[2]);
+    hipLaunchKernelGGL(k_cluster_flatten, dim3(nbs), dim3(kBlock), 0, st, label, N, size, n_clusters);
+    return hipGetLastError();
+}
+
 hipError_t launch_energy(const int64_t* C, const double* V, int R, int SKK, double* E, hipStream_t st)
 {
     hipLaunchKernelGGL(k_energy, dim3((unsigned)((R + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, C, V, R, SKK, E);

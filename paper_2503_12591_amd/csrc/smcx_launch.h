@@ -22,6 +22,10 @@ hipError_t launch_advance_counter(uint32_t* counter, uint32_t n, hipStream_t st)
 hipError_t launch_pair_counts(int lattice, int K, int S, const uint8_t* occ, int64_t N, const int32_t* L,
                               int B, int64_t* counts, hipStream_t st);
 hipError_t launch_energy(const int64_t* C, const double* V, int R, int SKK, double* E, hipStream_t st);
+hipError_t launch_local_energy(int lattice, const uint8_t* occ, const int32_t* L, int K, int S, const double* V,
+                               double* e, hipStream_t st);
+hipError_t launch_clusters(int lattice, const double* e, const int32_t* L, double threshold, int32_t* label,
+                           int32_t* size, int64_t* n_clusters, hipStream_t st);
 hipError_t launch_heat_capacity(const double* E, const double* beta_steps, const RepDev* reps, int n_steps, int n_rec,
                                 int R, double* cv, hipStream_t st);
 hipError_t launch_exchange(const double* E, const double* beta_slot, int32_t* rep_at, int R, uint64_t seed,

@@ -29,7 +29,7 @@ EXPORTS = [
     "smcx_pair_counts", "smcx_energy", "smcx_sro", "smcx_energy_backward", "smcx_ladder_capture",
     "smcx_sweep_capture",
     "smcx_graph_launch", "smcx_graph_destroy", "smcx_timing_enable", "smcx_timing_read",
-    "smcx_energy_dev", "smcx_exchange", "smcx_anneal",
+    "smcx_energy_dev", "smcx_exchange", "smcx_anneal", "smcx_local_energy", "smcx_clusters",
 ]
 
 
@@ -80,6 +80,8 @@ def lib():
     L.smcx_energy_dev.argtypes = [p, p, p, p]
     L.smcx_exchange.argtypes = [p, i32, u64, p, p, p, i32, p, p, p, p, i32, p, p]
     L.smcx_anneal.argtypes = [p, i32, i32, i32, u64, u32, p, p, p, p, p, p, i32, p, i32, p]
+    L.smcx_local_energy.argtypes = [p, i32, p, p]
+    L.smcx_clusters.argtypes = [p, i32, p, C.c_double, p, p, p, p]
     _lib = L
     return L
 
@@ -298,6 +300,28 @@ class Lattice:
                                  _ptr(tie_count), mode, _stream(torch)))
         self._last_beta = b
         return dict(E=E[:, :record], cv=cv, stats=stats, ties=ties, tie_count=tie_count)
+
+    def local_energy(self, r: int = 0, e=None):
+        """Per-site local energies of replica r (CUDA float64 [N_r])."""
+        if e is None:
+            e = self.torch.empty(int(self.N[r]), dtype=self.torch.float64, device="cuda")
+        _check(lib().smcx_local_energy(self.h, r, _ptr(e), _stream(self.torch)))
+        return e
+
+    def clusters(self, threshold: float, r: int = 0, e=None):
+        """Clusters of sites with local energy <= threshold in replica r:
+        (label int32 [N_r], size int32 [N_r], n_clusters int64 [1]) CUDA
+        tensors; e (local energies) is computed when not given."""
+        torch = self.torch
+        if e is None:
+            e = self.local_energy(r)
+        n = int(self.N[r])
+        label = torch.empty(n, dtype=torch.int32, device="cuda")
+        size = torch.empty(n, dtype=torch.int32, device="cuda")
+        nc = torch.zeros(1, dtype=torch.int64, device="cuda")
+        _check(lib().smcx_clusters(self.h, r, _ptr(e), C.c_double(threshold), _ptr(label), _ptr(size), _ptr(nc),
+                                   _stream(torch)))
+        return label, size, nc
 
     def sro(self) -> np.ndarray:
         a = np.zeros((self.R, self.S, self.K, self.K), np.float64)

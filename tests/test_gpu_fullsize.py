@@ -73,6 +73,42 @@ def test_large_bcc_ministeps_and_invariants(smcx):
         assert np.array_equal(C[sh].sum(axis=1), Z[sh] * w.counts)
     alpha = lat.sro()[0]
     assert np.all(np.abs(alpha) < 1.0)
+    say("bcc800: local energies (sampled against the oracle) and clusters (invariants)")
+    e = lat.local_energy()
+    E = float(lat.energy()[0])
+    assert abs(float(e.sum().item()) - E) <= 1e-9 * abs(E)
+    cur = work.cpu().numpy()
+    idx = np.random.default_rng(5).integers(0, w.N, 2000)
+    assert np.array_equal(e[torch.from_numpy(idx).cuda()].cpu().numpy(),
+                          O.local_energy_at(w.lattice, w.dims, w.K, w.S, cur, w.V, idx))
+    thr = float(torch.quantile(e[::4096].float(), 0.15).item())
+    label, size, nc = lat.clusters(thr, e=e)
+    marked = e <= thr
+    n_marked = int(marked.sum().item())
+    assert int(size.sum(dtype=torch.int64).item()) == n_marked
+    assert int((label >= 0).sum().item()) == n_marked
+    ar = torch.arange(w.N, device="cuda", dtype=torch.int32)
+    roots = label == ar
+    assert int(roots.sum().item()) == int(nc.item()) == int((size > 0).sum().item())
+    assert bool((label <= ar).all().item())
+    lab = label.cpu().numpy()
+    # sampled marked sites: their label is a root, and every marked nearest
+    # neighbour carries the same label
+    nbr_tab = O.shells(w.lattice, 1)
+    for i in idx[:300]:
+        if lab[i] < 0:
+            continue
+        assert lab[lab[i]] == lab[i]
+        b = int(i % 2)
+        c = int(i // 2)
+        x, y, z = c % 800, (c // 800) % 800, c // 640000
+        for v in (np.array(nbr_tab[1]).reshape(-1, 3)[:8]):
+            hx, hy, hz = 2 * x + b + v[0], 2 * y + b + v[1], 2 * z + b + v[2]
+            hx, hy, hz = hx % 1600, hy % 1600, hz % 1600
+            bt = hx & 1
+            j = bt + 2 * ((hx - bt) // 2 + 800 * ((hy - bt) // 2 + 800 * ((hz - bt) // 2)))
+            if lab[j] >= 0:
+                assert lab[j] == lab[i], (i, j)
     lat.close()
 
 

@@ -40,6 +40,8 @@ def test_local_energy_brute_force(oracle, lattice, dims, K, S, seed):
     assert np.allclose(e, ref, rtol=1e-12, atol=1e-15)
     E = brute.energy_from_table(nbr, occ, V)
     assert abs(math.fsum(e.tolist()) - E) <= 1e-12 * max(1.0, abs(E))
+    idx = np.random.default_rng(seed).integers(0, N, 25)
+    assert np.array_equal(oracle.local_energy_at(lattice, dims, K, S, occ, V, idx), e[idx])
 
 
 def reference_clusters(lattice, dims, e, thr):

@@ -51,7 +51,7 @@ MUTANTS = [
       "test_oracle_anneal.py::test_heat_capacity_exact_sixteen_site_cell"]),
     ("heat capacity from the sample variance", "v = v / (double)n;", "v = v / (double)(n - 1);",
      ["test_oracle_anneal.py::test_heat_capacity_closed_forms"]),
-    ("local energy without the 1/2", "e[i] = 0.5 * acc;", "e[i] = acc;",
+    ("local energy without the 1/2", "return acc * 0.5;", "return acc;",
      ["test_oracle_clusters.py::test_local_energy_brute_force"]),
     ("cluster labelled by the site that reached it", "label[j] = (int32_t)i;", "label[j] = (int32_t)a;",
      ["test_oracle_clusters.py::test_clusters_against_connected_components"]),
