@@ -227,6 +227,9 @@ def main():
         out["tempering"] = tempering_bench(args)
         print("[bench] anneal", file=sys.stderr, flush=True)
         out["anneal"] = anneal_bench(args)
+    if not args.no_ladder:
+        print("[bench] clusters", file=sys.stderr, flush=True)
+        out["clusters"] = clusters_bench(lat, N)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(lattice, dims, K, S, cells, occ_host, V, seed, beta,
@@ -400,6 +403,37 @@ def anneal_bench(args, warmup: int = 5, record: int = 5):
             "warmup": warmup, "record": record, "unit": "attempted swaps/s",
             "swaps_per_s": n_sweeps * wl.N / secs, "ms": secs * 1e3,
             "sweeps_only_ms": plain * 1e3, "records": len(T) * record}
+
+
+def clusters_bench(lat, N):
+    """The paper's analysis step on the benchmark lattice as the timed steps
+    left it: per-site local energies (smcx_local_energy), then the clusters of
+    the sites at or below the 15 % quantile of the local energy
+    (smcx_clusters: union-find over nearest neighbours).  Local energies move
+    9 algorithmic bytes per site (1 read, 8 written)."""
+    import torch
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3, r
+
+    e = lat.local_energy()  # warm-up
+    t_e, e = timed(lambda: lat.local_energy(e=e))
+    thr = float(torch.quantile(e[::4096].float(), 0.15).item())
+    lat.clusters(thr, e=e)  # warm-up
+    t_c, (label, size, nc) = timed(lambda: lat.clusters(thr, e=e))
+    out = {"workload": "local energies and clusters of the benchmark lattice (threshold: 15 % quantile)",
+           "sites": N, "local_energy_ms": t_e * 1e3, "local_energy_GBps": 9.0 * N / t_e / 1e9,
+           "clusters_ms": t_c * 1e3, "sites_per_s": N / t_c,
+           "marked_fraction": float((label >= 0).sum().item()) / N, "clusters": int(nc.item()),
+           "largest": int(size.max().item())}
+    del e, label, size
+    return out
 
 
 def algorithmic_bytes_per_launch(cells, N, m, launches_per_sweep):

@@ -1791,16 +1791,19 @@ __device__ __forceinline__ void par_store(int32_t* p, int32_t v)
 }
 
 // Root of x.  HALVE: point x at its grandparent on the way (while trees
-// still merge any ancestor will do); without it the walk only reads, as the
-// final labelling needs: there a halving store racing with the owner's
-// store of the root could leave an older ancestor as the label.
+// still merge any ancestor will do); without it the walk only reads: in the
+// final labelling a halving store could race with a store of the root and
+// leave an older ancestor as a label, so there the path is pointed at the
+// root instead, which every writer agrees on.
+// (The final labelling reads with plain loads: the trees no longer change,
+// and an out-of-date entry is still an ancestor.)
 template <bool HALVE>
 __device__ __forceinline__ int32_t cluster_find(int32_t* parent, int32_t x)
 {
     while (true) {
-        const int32_t p = par_load(parent + x);
+        const int32_t p = HALVE ? par_load(parent + x) : parent[x];
         if (p == x) return x;
-        const int32_t gp = par_load(parent + p);
+        const int32_t gp = HALVE ? par_load(parent + p) : parent[p];
         if (HALVE && gp != p) par_store(parent + x, gp);  // gp is an ancestor of x
         x = gp;
     }
@@ -1821,7 +1824,7 @@ __device__ __forceinline__ void cluster_hook_site(int32_t* parent, int c, int L0
     constexpr int m = G.m;
     if constexpr (B < m) {
         const int i = B + m * c;
-        if (par_load(parent + i) >= 0) {
+        if (parent[i] >= 0) {  // marks never change during the unions: a plain load will do
             const int x = c % L0, cr = c / L0, y = cr % L1, z = cr / L1;
 #pragma unroll
             for (int n = 0; n < G.Z[0]; ++n) {
@@ -1831,7 +1834,7 @@ __device__ __forceinline__ void cluster_hook_site(int32_t* parent, int c, int L0
                 yy += yy < 0 ? L1 : (yy >= L1 ? -L1 : 0);
                 zz += zz < 0 ? L2 : (zz >= L2 ? -L2 : 0);
                 const int j = nb.bt + m * (xx + L0 * (yy + L1 * zz));
-                if (j <= i || par_load(parent + j) < 0) continue;  // each marked pair once
+                if (j <= i || parent[j] < 0) continue;  // each marked pair once
                 int a = i, b = j;
                 while (true) {
                     a = cluster_find<true>(parent, a);
@@ -1866,9 +1869,15 @@ __global__ void k_cluster_flatten(int32_t* parent, int N, int32_t* size, int64_t
 {
     int roots = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
-        if (par_load(parent + i) < 0) continue;
-        const int32_t r = cluster_find<false>(parent, i);  // the trees are final; only site i's own entry is written
-        par_store(parent + i, r);
+        if (parent[i] < 0) continue;
+        // the trees are final, each with one root: point the whole path at
+        // the root (every thread that writes an entry writes that same root)
+        const int32_t r = cluster_find<false>(parent, i);
+        for (int32_t x = i; x != r;) {
+            const int32_t next = parent[x];
+            parent[x] = r;
+            x = next;
+        }
         atomicAdd(size + r, 1);
         roots += r == i;
     }
@@ -1902,7 +1911,8 @@ hipError_t launch_clusters(int lattice, const double* e, const int32_t* L, doubl
         hipLaunchKernelGGL(k_cluster_hook<SMCX_BCC>, dim3(nbc), dim3(kBlock), 0, st, label, L[0], L[1], L[2]);
     else
         hipLaunchKernelGGL(k_cluster_hook<SMCX_FCC>, dim3(nbc), dim3(kBlock), 0, st, label, L[0], L[1], L[2]);
-    hipLaunchKernelGGL(k_cluster_flatten, dim3(nbs), dim3(kBlock), 0, st, label, N, size, n_clusters);
+    // a grid-stride grid of 4096 workgroups: one count atomic per wave, not per 256 sites
+    hipLaunchKernelGGL(k_cluster_flatten, dim3(std::min(nbs, 4096u)), dim3(kBlock), 0, st, label, N, size, n_clusters);
     return hipGetLastError();
 }
 
