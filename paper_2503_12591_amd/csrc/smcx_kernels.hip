@@ -720,6 +720,30 @@ __device__ __forceinline__ void flush_stats(const SweepArgs& A, int r, Stats& st
     st = Stats();
 }
 
+// The same for a whole workgroup at a point every thread reaches: the waves'
+// sums meet in LDS and one thread adds them to the replica's counters (one
+// global atomic per counter and workgroup instead of per wave).
+__device__ __forceinline__ void flush_stats_block(const SweepArgs& A, int r, Stats& st)
+{
+    __shared__ int red[3];
+    if (threadIdx.x == 0) red[0] = red[1] = red[2] = 0;
+    __syncthreads();
+    const int a = wave_sum_i(st.att), c = wave_sum_i(st.acc), t = wave_sum_i(st.tie);
+    if ((threadIdx.x & 63) == 0) {
+        if (a) atomicAdd(&red[0], a);
+        if (c) atomicAdd(&red[1], c);
+        if (t) atomicAdd(&red[2], t);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && r >= 0) {
+        unsigned long long* p = (unsigned long long*)(A.stats + 3 * (int64_t)r);
+        if (red[0]) atomicAdd(p + 0, (unsigned long long)red[0]);
+        if (red[1]) atomicAdd(p + 1, (unsigned long long)red[1]);
+        if (red[2]) atomicAdd(p + 2, (unsigned long long)red[2]);
+    }
+    st = Stats();
+}
+
 // Block barrier that orders LDS accesses only: global loads issued before it
 // stay in flight (a full __syncthreads also drains them).
 __device__ __forceinline__ void lds_barrier()
@@ -1129,7 +1153,7 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (r != r_stats) {
-            flush_stats(A, r_stats, st);
+            flush_stats_block(A, r_stats, st);
             r_stats = r;
         }
         int tau = g0, b = b0, ox = ox0;
@@ -1147,7 +1171,7 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
         __syncthreads();  // every trial's window writes are visible
         if (row_yz) rows_writeback<LAT, Geo>(A, rep, tg, lx, T0, y0 + oy, z0 + oz, A.ws + rep.pad_off, win);
     }
-    flush_stats(A, r_stats, st);
+    flush_stats_block(A, r_stats, st);
 }
 
 // ---------------------------------------------------------------------------
