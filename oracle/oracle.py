@@ -81,6 +81,10 @@ def lib():
         L.or_local_energy.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, p]
         L.or_clusters.argtypes = [C.c_int, p, p, dbl, p, p, p, p]
         L.or_local_energy_at.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, p, i64, p]
+        L.or_run_qsro.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, p, p, p, u64, u32, u32, i32, p, p, i32,
+                                  p, p, i32, p, i32]
+        L.or_qsro_local_energy.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, p, p]
+        L.or_qsro_delta_e.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, p, i64, i32, p, p]
         _lib = L
     return _lib
 
@@ -381,3 +385,49 @@ def clusters(lattice, dims, e, threshold: float):
                          _ptr(nc), _ptr(stack)) != 0:
         raise ValueError("or_clusters failed")
     return label, size, int(nc[0])
+
+
+def run_qsro(lattice, dims, K, S, cells, occ: np.ndarray, V, W, seed: int, betas, first_sweep: int = 0,
+             replica: int = 0, replay=None, tie_cap: int = 1024, nthreads: int = 1) -> RunResult:
+    """Sweeps under the qSRO model (``or_run_qsro``), in place on ``occ``."""
+    assert occ.dtype == np.uint8 and occ.flags.c_contiguous
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    betas = np.ascontiguousarray(np.asarray(betas, dtype=np.float64).reshape(-1))
+    ncell = np.array([len(c) for c in cells], np.int32)
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(c, np.int32) for c in cells]))
+    if replay is None:
+        replay = np.zeros(0, TIE_DTYPE)
+    replay = np.ascontiguousarray(replay, dtype=TIE_DTYPE)
+    stats = np.zeros(3, np.int64)
+    ties = np.zeros(max(tie_cap, 1), TIE_DTYPE)
+    n_ties = np.zeros(1, np.int32)
+    rc = lib().or_run_qsro(lattice, _ptr(_dims(dims)), K, S, _ptr(ncell), _ptr(flat), _ptr(occ), _ptr(V),
+                           _ptr(W), seed, replica, first_sweep, len(betas), _ptr(betas), _ptr(replay),
+                           len(replay), _ptr(stats), _ptr(ties), tie_cap, _ptr(n_ties), nthreads)
+    if rc != 0:
+        raise ValueError("or_run_qsro failed (bad arguments or an edge <= c_max + 1)")
+    nt = int(n_ties[0])
+    return RunResult(stats, ties[:min(nt, tie_cap)].copy(), nt, None)
+
+
+def qsro_local_energy(lattice, dims, K, S, occ, V, W) -> np.ndarray:
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    e = np.zeros(len(occ), np.float64)
+    if lib().or_qsro_local_energy(lattice, _ptr(_dims(dims)), K, S, _ptr(occ), _ptr(V), _ptr(W), _ptr(e)) != 0:
+        raise ValueError("or_qsro_local_energy failed")
+    return e
+
+
+def qsro_delta_e(lattice, dims, K, S, occ, V, W, a: int, k: int):
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    dE = np.zeros(1, np.float64)
+    b = np.zeros(1, np.int64)
+    if lib().or_qsro_delta_e(lattice, _ptr(_dims(dims)), K, S, _ptr(occ), _ptr(V), _ptr(W), a, k, _ptr(dE),
+                             _ptr(b)) != 0:
+        raise ValueError("or_qsro_delta_e failed")
+    return float(dE[0]), int(b[0])

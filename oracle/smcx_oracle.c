@@ -410,6 +410,109 @@ static double trial_dE(const or_sys *sy, const uint8_t *occ, const double *V, in
     return dE;
 }
 
+/* ------------------------------------------------------------------------ */
+/* qSRO model: a nonlinear local energy                                      */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * qSRO local energy of site i with species p (Methods, "The EPI and qSRO
+ * model", Eq. quadratic_local_SRO): the pair fractions of the local
+ * environment, pi_m^{p t} = n_i[m][t] / Z_m (centre-neighbour pairs of shell
+ * m), enter linearly with V_m[p][t] and, for the same-species pair, squared
+ * with W_m[p]:
+ *   E_i = sum_m sum_t V_m[p][t] (n_i[m][t] / Z_m) + sum_m W_m[p] (n_i[m][p] / Z_m)^2,
+ * in that order (m, then t), each quotient, product and sum rounded.
+ */
+static double qsro_site(const or_sys *sy, const uint8_t *occ, const double *V, const double *W, int64_t i)
+{
+    int K = sy->K, S = sy->S;
+    int h[3];
+    site_pos(sy, i, h);
+    int n[OR_MAXS][OR_MAXK];
+    memset(n, 0, sizeof(n));
+    for (int s = 0; s < S; ++s)
+        for (int k = 0; k < sy->Z[s]; ++k) n[s][occ[site_at(sy, h, sy->d[s][k])]] += 1;
+    int p = occ[i];
+    double acc = 0.0;
+    for (int s = 0; s < S; ++s)
+        for (int t = 0; t < K; ++t) acc = acc + V[((size_t)s * K + p) * K + t] * ((double)n[s][t] / (double)sy->Z[s]);
+    for (int s = 0; s < S; ++s) {
+        double f = (double)n[s][p] / (double)sy->Z[s];
+        acc = acc + W[(size_t)s * K + p] * (f * f);
+    }
+    return acc;
+}
+
+/* Displacements (half units, from the active site a) of every site whose
+ * qSRO local energy a swap of a with its partner in direction D_1[k] can
+ * change: a, the partner, and every shell neighbour of either; without
+ * duplicates, in lexicographic (x, y, z) order.  Returns the count. */
+#define OR_MAXAFF 256
+static int qsro_affected(const or_sys *sy, int k, int (*v)[3])
+{
+    int n = 0;
+    int cand[2 + 2 * OR_MAXS * OR_MAXZ][3];
+    const int *ab = sy->d[0][k];
+    cand[n][0] = cand[n][1] = cand[n][2] = 0;
+    ++n;
+    for (int a = 0; a < 3; ++a) cand[n][a] = ab[a];
+    ++n;
+    for (int s = 0; s < sy->S; ++s)
+        for (int j = 0; j < sy->Z[s]; ++j) {
+            for (int a = 0; a < 3; ++a) cand[n][a] = sy->d[s][j][a];
+            ++n;
+            for (int a = 0; a < 3; ++a) cand[n][a] = ab[a] + sy->d[s][j][a];
+            ++n;
+        }
+    int m = 0;
+    for (int i = 0; i < n; ++i) {
+        int dup = 0;
+        for (int j = 0; j < m && !dup; ++j)
+            dup = v[j][0] == cand[i][0] && v[j][1] == cand[i][1] && v[j][2] == cand[i][2];
+        if (dup) continue;
+        /* insert in lexicographic order */
+        int at = m;
+        while (at > 0 && (v[at - 1][0] > cand[i][0] ||
+                          (v[at - 1][0] == cand[i][0] && (v[at - 1][1] > cand[i][1] ||
+                                                          (v[at - 1][1] == cand[i][1] && v[at - 1][2] > cand[i][2]))))) {
+            for (int a = 0; a < 3; ++a) v[at][a] = v[at - 1][a];
+            --at;
+        }
+        for (int a = 0; a < 3; ++a) v[at][a] = cand[i][a];
+        ++m;
+    }
+    return m;
+}
+
+/* qSRO energy change of swapping a with its partner b = a + D_1[k]: the
+ * local energies of the affected sites before and after the swap (computed
+ * on the swapped occupancy, which is then restored), summed as
+ * dE = dE + (after_j - before_j) over the affected set in its order.  The
+ * paper's rule for models beyond pairs: add up the local energies of every
+ * site within the interaction zone (Methods, text before
+ * Eq. quadratic_local_SRO). */
+static double qsro_dE(const or_sys *sy, uint8_t *occ, const double *V, const double *W, int64_t a, int64_t b, int k)
+{
+    int v[OR_MAXAFF][3];
+    int n = qsro_affected(sy, k, v);
+    int ha[3];
+    site_pos(sy, a, ha);
+    int64_t js[OR_MAXAFF];
+    double before[OR_MAXAFF];
+    for (int i = 0; i < n; ++i) {
+        js[i] = site_at(sy, ha, v[i]);
+        before[i] = qsro_site(sy, occ, V, W, js[i]);
+    }
+    uint8_t p = occ[a], q = occ[b];
+    occ[a] = q;
+    occ[b] = p;
+    double dE = 0.0;
+    for (int i = 0; i < n; ++i) dE = dE + (qsro_site(sy, occ, V, W, js[i]) - before[i]);
+    occ[a] = p;
+    occ[b] = q;
+    return dE;
+}
+
 /* The 53-bit uniform of a trial or exchange: (w1 2^21 + floor(w2 / 2^11)) 2^-53. */
 static double u53(const uint32_t w[4])
 {
@@ -440,7 +543,7 @@ static int replay_lookup(const or_replay *rp, int32_t r, uint32_t t, int64_t a, 
  * (Supplementary, "Monte Carlo Simulation Algorithms"): a uniform nearest
  * neighbour partner, Metropolis acceptance, swap on acceptance.
  */
-static int do_trial(const or_sys *sy, uint8_t *occ, const double *V, uint64_t seed, uint32_t r,
+static int do_trial(const or_sys *sy, uint8_t *occ, const double *V, const double *W, uint64_t seed, uint32_t r,
                     uint32_t t, int64_t a, double beta, const or_replay *rp, or_trace *tr)
 {
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -455,7 +558,7 @@ static int do_trial(const or_sys *sy, uint8_t *occ, const double *V, uint64_t se
     int flags = 0;
     double dE = 0.0;
     if (p != q) {
-        dE = trial_dE(sy, occ, V, a, b);
+        dE = W ? qsro_dE(sy, occ, V, W, a, b, k) : trial_dE(sy, occ, V, a, b);
         int accept;
         if (dE <= 0.0) {
             accept = 1;
@@ -510,7 +613,7 @@ int or_single_trial(int lattice, const int32_t L[3], int K, int S, uint8_t *occ,
     or_sys sy;
     if (sys_init(&sy, lattice, L, K, S) != OR_OK) return OR_EARG;
     if (a < 0 || a >= sy.N) return OR_EARG;
-    return do_trial(&sy, occ, V, seed, replica, sweep, a, beta, NULL, NULL);
+    return do_trial(&sy, occ, V, NULL, seed, replica, sweep, a, beta, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -539,7 +642,7 @@ int or_single_trial(int lattice, const int32_t L[3], int K, int S, uint8_t *occ,
  * trials within a mini-step are independent, so the result is identical.
  */
 static int run_range(int lattice, const int32_t L[3], int K, int S, const int32_t ncell[3],
-                     const int32_t *cells, uint8_t *occ, const double *V, uint64_t seed,
+                     const int32_t *cells, uint8_t *occ, const double *V, const double *W, uint64_t seed,
                      uint32_t replica, uint32_t first_sweep, int32_t n_sweeps, int32_t tau_begin,
                      int32_t tau_end, const double *beta, const or_tie *replay, int32_t n_replay,
                      int64_t *stats, or_tie *ties, int32_t tie_cap, int32_t *n_ties, or_trace *trace,
@@ -609,7 +712,7 @@ static int run_range(int lattice, const int32_t L[3], int K, int S, const int32_
                     int64_t a = site_index(&sy, b, origin[0][cx] + o[0], origin[1][cy] + o[1],
                                            origin[2][cz] + o[2]);
                     or_trace *tr = (trace && ntrace < trace_cap) ? &trace[ntrace] : NULL;
-                    int f = do_trial(&sy, occ, V, seed, replica, t, a, bt, &rp, tr);
+                    int f = do_trial(&sy, occ, V, W, seed, replica, t, a, bt, &rp, tr);
                     if (trace) ++ntrace;
                     att += 1;
                     if (f & TR_ACCEPTED) acc += 1;
@@ -635,7 +738,7 @@ static int run_range(int lattice, const int32_t L[3], int K, int S, const int32_
                     if (o[0] >= edge[0][cx] || o[1] >= edge[1][cy] || o[2] >= edge[2][cz]) continue;
                     int64_t a = site_index(&sy, b, origin[0][cx] + o[0], origin[1][cy] + o[1],
                                            origin[2][cz] + o[2]);
-                    int f = do_trial(&sy, occ, V, seed, replica, t, a, bt, &rp, NULL);
+                    int f = do_trial(&sy, occ, V, W, seed, replica, t, a, bt, &rp, NULL);
                     att_l += 1;
                     if (f & TR_ACCEPTED) acc_l += 1;
                     if (f & TR_TIE) {
@@ -673,7 +776,7 @@ int or_run(int lattice, const int32_t L[3], int K, int S, const int32_t ncell[3]
            int32_t n_replay, int64_t *stats, or_tie *ties, int32_t tie_cap, int32_t *n_ties,
            or_trace *trace, int64_t trace_cap, int32_t nthreads)
 {
-    return run_range(lattice, L, K, S, ncell, cells, occ, V, seed, replica, first_sweep, n_sweeps, 0,
+    return run_range(lattice, L, K, S, ncell, cells, occ, V, NULL, seed, replica, first_sweep, n_sweeps, 0,
                      0x7fffffff, beta, replay, n_replay, stats, ties, tie_cap, n_ties, trace,
                      trace_cap, nthreads);
 }
@@ -687,9 +790,75 @@ int or_run_ministeps(int lattice, const int32_t L[3], int K, int S, const int32_
                      const or_tie *replay, int32_t n_replay, int64_t *stats, or_tie *ties,
                      int32_t tie_cap, int32_t *n_ties, int32_t nthreads)
 {
-    return run_range(lattice, L, K, S, ncell, cells, occ, V, seed, replica, sweep, 1, tau_begin,
+    return run_range(lattice, L, K, S, ncell, cells, occ, V, NULL, seed, replica, sweep, 1, tau_begin,
                      tau_end, &beta, replay, n_replay, stats, ties, tie_cap, n_ties, NULL, 0,
                      nthreads);
+}
+
+/* Largest |component| (half units) over the S shells' vectors. */
+static int shell_reach(const or_sys *sy)
+{
+    int c = 0;
+    for (int s = 0; s < sy->S; ++s)
+        for (int n = 0; n < sy->Z[s]; ++n)
+            for (int a = 0; a < 3; ++a) {
+                int v = sy->d[s][n][a] < 0 ? -sy->d[s][n][a] : sy->d[s][n][a];
+                if (v > c) c = v;
+            }
+    return c;
+}
+
+/*
+ * Sweeps under the qSRO model (local energy qsro_site, V [S][K][K] and
+ * W [S][K]); otherwise as or_run.  The affected set of a swap must not fold
+ * onto itself through the periodic images, so every edge must exceed
+ * c_max + 1 conventional cells (returns OR_EARG otherwise).  The partition
+ * must satisfy the interaction-zone rule 2 l > 2 + 2 c_max (or_lmin with
+ * liz = 1) for its mini-steps to be independent; that is the caller's.
+ */
+int or_run_qsro(int lattice, const int32_t L[3], int K, int S, const int32_t ncell[3], const int32_t *cells,
+                uint8_t *occ, const double *V, const double *W, uint64_t seed, uint32_t replica,
+                uint32_t first_sweep, int32_t n_sweeps, const double *beta, const or_tie *replay, int32_t n_replay,
+                int64_t *stats, or_tie *ties, int32_t tie_cap, int32_t *n_ties, int32_t nthreads)
+{
+    or_sys sy;
+    if (!W || sys_init(&sy, lattice, L, K, S) != OR_OK) return OR_EARG;
+    int c = shell_reach(&sy);
+    for (int a = 0; a < 3; ++a)
+        if (L[a] <= c + 1) return OR_EARG;
+    return run_range(lattice, L, K, S, ncell, cells, occ, V, W, seed, replica, first_sweep, n_sweeps, 0, 0x7fffffff,
+                     beta, replay, n_replay, stats, ties, tie_cap, n_ties, NULL, 0, nthreads);
+}
+
+/* qSRO local energies of every site (for the pins), and the qSRO energy
+ * change of one swap of site a with its partner in direction k (occ is left
+ * unchanged; *b_out receives the partner). */
+int or_qsro_local_energy(int lattice, const int32_t L[3], int K, int S, const uint8_t *occ, const double *V,
+                         const double *W, double *e)
+{
+    or_sys sy;
+    if (sys_init(&sy, lattice, L, K, S) != OR_OK) return OR_EARG;
+    for (int64_t i = 0; i < sy.N; ++i)
+        if (occ[i] >= K) return OR_EARG;
+    for (int64_t i = 0; i < sy.N; ++i) e[i] = qsro_site(&sy, occ, V, W, i);
+    return OR_OK;
+}
+
+int or_qsro_delta_e(int lattice, const int32_t L[3], int K, int S, uint8_t *occ, const double *V, const double *W,
+                    int64_t a, int32_t k, double *dE, int64_t *b_out)
+{
+    or_sys sy;
+    if (sys_init(&sy, lattice, L, K, S) != OR_OK) return OR_EARG;
+    if (a < 0 || a >= sy.N || k < 0 || k >= sy.Z[0]) return OR_EARG;
+    int c = shell_reach(&sy);
+    for (int ax = 0; ax < 3; ++ax)
+        if (L[ax] <= c + 1) return OR_EARG;
+    int ha[3];
+    site_pos(&sy, a, ha);
+    int64_t b = site_at(&sy, ha, sy.d[0][k]);
+    *b_out = b;
+    *dE = occ[a] == occ[b] ? 0.0 : qsro_dE(&sy, occ, V, W, a, b, k);
+    return OR_OK;
 }
 
 /* Number of OpenMP threads available to the timing variant (1 without

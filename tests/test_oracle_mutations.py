@@ -57,6 +57,13 @@ MUTANTS = [
      ["test_oracle_clusters.py::test_clusters_against_connected_components"]),
     ("strict cluster threshold", "if (e[j] <= threshold && label[j] < 0) {", "if (e[j] < threshold && label[j] < 0) {",
      ["test_oracle_clusters.py::test_clusters_against_connected_components"]),
+    ("qSRO quadratic term not squared", "acc = acc + W[(size_t)s * K + p] * (f * f);", "acc = acc + W[(size_t)s * K + p] * f;",
+     ["test_oracle_qsro.py::test_closed_form_one_impurity"]),
+    ("qSRO affected set without the partner's neighbours",
+     "            for (int a = 0; a < 3; ++a) cand[n][a] = ab[a] + sy->d[s][j][a];\n            ++n;\n", "",
+     ["test_oracle_qsro.py::test_delta_e_is_the_total_energy_difference"]),
+    ("qSRO affected set with duplicates", "dup = v[j][0] == cand[i][0] && v[j][1] == cand[i][1] && v[j][2] == cand[i][2];",
+     "dup = 0;", ["test_oracle_qsro.py::test_delta_e_is_the_total_energy_difference"]),
 ]
 
 
