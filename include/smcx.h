@@ -264,6 +264,38 @@ int smcx_exchange(smcx_lattice *h, int32_t round, uint64_t seed, const double *b
  * enqueued on `stream` without host synchronisation.  Errors:
  * SMCX_E_INVALID_ARG (negative sizes, missing buffers, sweep index past
  * 2^32), SMCX_E_NOT_READY before smcx_set_epi. */
+/* qSRO model (Methods, "The EPI and qSRO model", Eq. quadratic_local_SRO):
+ * the local energy of a site with species p is
+ *   E_i = sum_m sum_t V_m[p][t] (n_i[m][t] / Z_m) + sum_m W_m[p] (n_i[m][p] / Z_m)^2
+ * (pair fractions of the centre-neighbour pairs of shell m; m, then t,
+ * ascending, binary64).  V [S][K][K] (symmetric) and W [S][K] are host
+ * arrays, copied.  Synchronises the stream.  Errors: SMCX_E_INVALID_ARG
+ * (NULL, asymmetric or non-finite V, non-finite W). */
+int smcx_set_qsro(smcx_lattice *h, const double *V, const double *W, void *stream);
+
+/* n_sweeps sweeps of every replica under the qSRO model, in the same
+ * mini-step order and with the same per-trial random numbers, partner and
+ * acceptance rule (near-tie log included) as smcx_sweep.  A swap changes the
+ * local energy of every site that has a or b in one of its shells, so its
+ * energy change is the sum of E_after - E_before over that affected set:
+ * a, b and every shell neighbour of either, without duplicates, in
+ * lexicographic order of the half-unit displacement from a (the paper's rule
+ * for models beyond pairs: add up the local energies of the interaction
+ * zone).  A wave takes one trial and its lanes the affected sites
+ * (sub-move parallelism).
+ *   beta_host [n_sweeps][R] binary64 (host).
+ *   stats_dev, ties_dev, tie_cap, tie_count_dev: as for smcx_sweep.
+ * Requirements: every link-cell edge (on axes of more than one cell) at
+ * least the interaction-zone minimum, the smallest l with 2 l > 2 + 2 c_max
+ * (c_max: largest shell-vector component in half units; 4 for BCC or FCC
+ * with 2 shells, 5 for BCC with 4), so that a mini-step's trials do not
+ * see each other's swaps; every edge above c_max + 1; fewer than 2^31 sites
+ * per replica.  Asynchronous.  Errors: SMCX_E_INVALID_ARG,
+ * SMCX_E_UNSUPPORTED, SMCX_E_NOT_READY before smcx_set_qsro. */
+int smcx_sweep_qsro(smcx_lattice *h, int32_t n_sweeps, uint64_t seed, uint32_t first_sweep,
+                    const double *beta_host, int64_t *stats_dev, smcx_tie *ties_dev, int32_t tie_cap,
+                    int32_t *tie_count_dev, void *stream);
+
 /* Local energy of every site of one replica: e_dev [N_r] binary64 receives
  * e_i = 1/2 sum_s sum_t n_i[s][t] V_s[sigma_i][t] (n_i[s][t]: shell-s
  * neighbours of species t, periodic images with multiplicity; s, t

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -98,6 +99,9 @@ struct Plan {
     int LP, WY, WZ;
     LdsLayout lds;
     size_t off_reps, off_origins, off_tileoff, off_offP, off_offB, off_pd, off_D, off_V, off_misc, off_pad, total;
+    // qSRO model: affected-set and neighbour tables, V, W, Z
+    size_t off_qaff, off_qnbr, off_qV, off_qW, off_qZ;
+    int qnaff;  // largest affected set
     int n_origins;
     int64_t total_sites, total_tiles;
     int max_nA;
@@ -380,6 +384,11 @@ int make_plan(const smcx_desc* d, Plan& P)
     P.off_D = o; o = align256(o + sizeof(double) * P.K * P.K * P.S * P.K);
     P.off_V = o; o = align256(o + sizeof(double) * P.S * P.K * P.K);
     P.off_misc = o; o = align256(o + 256);
+    P.off_qaff = o; o = align256(o + sizeof(int32_t) * P.m * P.Z1 * (1 + kQsroMaxAff));
+    P.off_qnbr = o; o = align256(o + sizeof(int32_t) * P.m * P.sumZ);
+    P.off_qV = o; o = align256(o + sizeof(double) * P.S * P.K * P.K);
+    P.off_qW = o; o = align256(o + sizeof(double) * P.S * P.K);
+    P.off_qZ = o; o = align256(o + sizeof(int32_t) * kMaxShells);
     P.off_rowoff = o; o = align256(o + sizeof(int64_t) * (P.R + 1));
     P.off_offP_r = o; o = align256(o + sizeof(int16_t) * P.m * P.Z1 * P.sumZ);
     P.off_offB_r = o; o = align256(o + sizeof(int32_t) * P.m * P.Z1);
@@ -417,6 +426,7 @@ struct smcx_lattice {
     uint8_t* ws;
     size_t ws_bytes;
     bool epi_set = false;
+    bool qsro_set = false;
     std::vector<double> V;       // [S][K][K]
     std::vector<double> Dhost;   // [S][K][K][K]: D[s][t][p][q]
     std::vector<int64_t> counts_host;
@@ -660,6 +670,55 @@ int smcx_lattice_init(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_de
     SMCX_HIP(hipMemcpyAsync(h->ws + P.off_rowoff, row_off.data(), sizeof(int64_t) * row_off.size(), hipMemcpyHostToDevice, st));
     SMCX_HIP(hipMemcpyAsync(h->ws + P.off_offP_r, offP_r.data(), sizeof(int16_t) * offP_r.size(), hipMemcpyHostToDevice, st));
     SMCX_HIP(hipMemcpyAsync(h->ws + P.off_offB_r, offB_r.data(), sizeof(int32_t) * offB_r.size(), hipMemcpyHostToDevice, st));
+    {
+        // qSRO tables.  Neighbours of a basis-b site, shells in order; the
+        // affected set of a swap of a basis-B site with its partner k: the
+        // half-unit displacements 0, D_1[k], D_s[n] and D_1[k] + D_s[n],
+        // without duplicates, in lexicographic (x, y, z) order (the order in
+        // which a trial adds up the local-energy changes).
+        const Geometry& G = kGeom[P.lattice];
+        auto pack = [&](int b, int vx, int vy, int vz) {
+            const Nb nb = nb_of(G, b, vx, vy, vz);
+            return (int32_t)((nb.dx + 8) | (nb.dy + 8) << 8 | (nb.dz + 8) << 16 | nb.bt << 24);
+        };
+        std::vector<int32_t> qnbr((size_t)P.m * P.sumZ), qaff((size_t)P.m * P.Z1 * (1 + kQsroMaxAff), 0);
+        for (int b = 0; b < P.m; ++b) {
+            int j = 0;
+            for (int sh = 0; sh < P.S; ++sh)
+                for (int n = 0; n < G.Z[sh]; ++n) qnbr[(size_t)b * P.sumZ + j++] = pack(b, G.v[sh][n][0], G.v[sh][n][1], G.v[sh][n][2]);
+        }
+        int largest = 0;
+        for (int b = 0; b < P.m; ++b)
+            for (int k = 0; k < P.Z1; ++k) {
+                std::vector<std::array<int, 3>> v;
+                auto add = [&](int x, int y, int z) {
+                    const std::array<int, 3> d{x, y, z};
+                    if (std::find(v.begin(), v.end(), d) == v.end()) v.push_back(d);
+                };
+                const int* ab = G.v[0][k];
+                add(0, 0, 0);
+                add(ab[0], ab[1], ab[2]);
+                for (int sh = 0; sh < P.S; ++sh)
+                    for (int n = 0; n < G.Z[sh]; ++n) {
+                        const int* d = G.v[sh][n];
+                        add(d[0], d[1], d[2]);
+                        add(ab[0] + d[0], ab[1] + d[1], ab[2] + d[2]);
+                    }
+                std::sort(v.begin(), v.end());
+                if ((int)v.size() > kQsroMaxAff) return fail(SMCX_E_UNSUPPORTED, "qSRO affected set too large");
+                int32_t* row = qaff.data() + (size_t)(b * P.Z1 + k) * (1 + kQsroMaxAff);
+                row[0] = (int32_t)v.size();
+                for (size_t i = 0; i < v.size(); ++i) row[1 + i] = pack(b, v[i][0], v[i][1], v[i][2]);
+                largest = std::max(largest, (int)v.size());
+            }
+        h->P.qnaff = largest;
+        int32_t Zs[kMaxShells] = {0, 0, 0, 0};
+        for (int sh = 0; sh < P.S; ++sh) Zs[sh] = G.Z[sh];
+        SMCX_HIP(hipMemcpyAsync(h->ws + P.off_qnbr, qnbr.data(), sizeof(int32_t) * qnbr.size(), hipMemcpyHostToDevice, st));
+        SMCX_HIP(hipMemcpyAsync(h->ws + P.off_qaff, qaff.data(), sizeof(int32_t) * qaff.size(), hipMemcpyHostToDevice, st));
+        SMCX_HIP(hipMemcpyAsync(h->ws + P.off_qZ, Zs, sizeof(Zs), hipMemcpyHostToDevice, st));
+        SMCX_HIP(hipStreamSynchronize(st));  // the host tables go out of scope
+    }
     int32_t* bad = (int32_t*)(h->ws + P.off_misc);
     SMCX_HIP(launch_fill_i32(bad, 1, 0, st));
     SMCX_HIP(launch_validate(occ_dev, P.total_sites, P.K, bad, st));
@@ -750,6 +809,100 @@ int smcx_set_epi(smcx_lattice* h, const double* V, void* stream)
     SMCX_HIP(hipMemcpyAsync(h->ws + P.off_V, h->V.data(), sizeof(double) * h->V.size(), hipMemcpyHostToDevice, st));
     SMCX_HIP(hipStreamSynchronize(st));
     h->epi_set = true;
+    return SMCX_OK;
+}
+
+int smcx_set_qsro(smcx_lattice* h, const double* V, const double* W, void* stream)
+{
+    if (int rc = check_handle(h)) return rc;
+    if (!V || !W) return fail(SMCX_E_INVALID_ARG, "V and W are required");
+    const Plan& P = h->P;
+    const int K = P.K, S = P.S;
+    for (int s = 0; s < S; ++s)
+        for (int k = 0; k < K; ++k) {
+            if (!std::isfinite(W[s * K + k])) return fail(SMCX_E_INVALID_ARG, "W must be finite");
+            for (int l = 0; l < K; ++l) {
+                const double a = V[(s * K + k) * K + l], b = V[(s * K + l) * K + k];
+                if (!(a == b)) return fail(SMCX_E_INVALID_ARG, "V must be symmetric in its species indices (and finite)");
+            }
+        }
+    hipStream_t st = (hipStream_t)stream;
+    SMCX_HIP(hipMemcpyAsync(h->ws + P.off_qV, V, sizeof(double) * S * K * K, hipMemcpyHostToDevice, st));
+    SMCX_HIP(hipMemcpyAsync(h->ws + P.off_qW, W, sizeof(double) * S * K, hipMemcpyHostToDevice, st));
+    SMCX_HIP(hipStreamSynchronize(st));
+    h->qsro_set = true;
+    return SMCX_OK;
+}
+
+int smcx_sweep_qsro(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t first_sweep, const double* beta_host,
+                    int64_t* stats_dev, smcx_tie* ties_dev, int32_t tie_cap, int32_t* tie_count_dev, void* stream)
+{
+    if (int rc = check_handle(h)) return rc;
+    if (!h->qsro_set) return fail(SMCX_E_NOT_READY, "smcx_set_qsro has not been called");
+    if (n_sweeps < 0) return fail(SMCX_E_INVALID_ARG, "n_sweeps must be >= 0");
+    if (n_sweeps > 0 && !beta_host) return fail(SMCX_E_INVALID_ARG, "beta_host is required");
+    if (!stats_dev || !tie_count_dev) return fail(SMCX_E_INVALID_ARG, "stats and tie_count are required");
+    if (tie_cap < 0 || (tie_cap > 0 && !ties_dev)) return fail(SMCX_E_INVALID_ARG, "ties_dev required when tie_cap > 0");
+    const Plan& P = h->P;
+    const Geometry& G = kGeom[P.lattice];
+    // reach: largest |component| (half units) of the S shells' vectors
+    int c = 0;
+    for (int s = 0; s < P.S; ++s)
+        for (int n = 0; n < G.Z[s]; ++n)
+            for (int a = 0; a < 3; ++a) c = std::max(c, std::abs(G.v[s][n][a]));
+    int ell = 1;
+    while (!(2 * ell > 2 + 2 * c)) ++ell;  // interaction-zone rule
+    for (const Replica& R : P.reps) {
+        if (R.N > 0x7fffffffLL) return fail(SMCX_E_UNSUPPORTED, "qSRO sweeps need fewer than 2^31 sites per replica");
+        for (int a = 0; a < 3; ++a) {
+            if (R.L[a] <= c + 1) return fail(SMCX_E_INVALID_ARG, "qSRO needs every edge above the shells' reach + 1");
+            if (R.edges[a].size() > 1)
+                for (int e : R.edges[a])
+                    if (e < ell)
+                        return fail(SMCX_E_INVALID_ARG, "qSRO needs link cells of edge >= " + std::to_string(ell) +
+                                                            " (interaction-zone rule); pass ell or cells accordingly");
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t* origins = (const int32_t*)(h->ws + P.off_origins);
+    std::vector<int> cs_off(P.R, 0);  // each replica's cell origins: nc + 1 entries per axis
+    for (int r = 1; r < P.R; ++r) {
+        const Replica& Q = P.reps[r - 1];
+        cs_off[r] = cs_off[r - 1] + (int)(Q.origin[0].size() + Q.origin[1].size() + Q.origin[2].size());
+    }
+    for (int js = 0; js < n_sweeps; ++js)
+        for (int r = 0; r < P.R; ++r) {
+            const Replica& R = P.reps[r];
+            QsroArgs A{};
+            A.occ = h->occ + R.occ_off;
+            A.L0 = R.L[0]; A.L1 = R.L[1]; A.L2 = R.L[2];
+            A.K = P.K; A.S = P.S; A.Z1 = P.Z1; A.sumZ = P.sumZ; A.naff_max = kQsroMaxAff;
+            A.ncx = (int)R.edges[0].size(); A.ncy = (int)R.edges[1].size(); A.ncz = (int)R.edges[2].size();
+            A.org = origins + cs_off[r];
+            A.sweep = first_sweep + (uint32_t)js;
+            A.replica = (uint32_t)r;
+            A.seed = seed;
+            A.beta = beta_host[(int64_t)js * P.R + r];
+            A.aff = (const int32_t*)(h->ws + P.off_qaff);
+            A.nbr = (const int32_t*)(h->ws + P.off_qnbr);
+            A.V = (const double*)(h->ws + P.off_qV);
+            A.W = (const double*)(h->ws + P.off_qW);
+            A.Z = (const int32_t*)(h->ws + P.off_qZ);
+            A.stats = stats_dev + 3 * (int64_t)r;
+            A.ties = ties_dev;
+            A.tie_cap = tie_cap;
+            A.tie_count = tie_count_dev;
+            const int ncell = A.ncx * A.ncy * A.ncz;
+            const int grid = std::min(ncell, 8192);
+            for (int tau = 0; tau < R.nA; ++tau) {
+                A.b = tau % P.m;
+                const int rest = tau / P.m;
+                A.o0 = rest % R.M[0];
+                A.o1 = (rest / R.M[0]) % R.M[1];
+                A.o2 = rest / (R.M[0] * R.M[1]);
+                SMCX_HIP(launch_qsro_ministep(P.lattice, A, grid, st));
+            }
+        }
     return SMCX_OK;
 }
 

@@ -1940,6 +1940,146 @@ hipError_t launch_clusters(int lattice, const double* e, const int32_t* L, doubl
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// qSRO model: trials whose energy change needs every local energy of the
+// swap's interaction zone.  E_i = sum_m sum_t V_m[p][t] (n_i[m][t] / Z_m)
+// + sum_m W_m[p] (n_i[m][p] / Z_m)^2 (p = sigma_i; m, then t, ascending,
+// binary64).  A wave takes one trial (the same Philox draw, partner and
+// acceptance rule as the pair model); its lanes take the sites of the
+// affected set (a, the partner and every shell neighbour of either, in the
+// host table's order), recount each one's neighbours before and after the
+// swap (the swap applied to the two sites on the fly) and leave
+// E_after - E_before in LDS; lane 0 adds the terms in table order, decides
+// and writes the swap.  The sites are read from the natural layout; the
+// partition keeps every read of a mini-step's trial clear of the other
+// trials' writes (interaction-zone rule).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int qsro_site_of(const QsroArgs& A, int x, int y, int z, int32_t d, int m)
+{
+    // d packs (dx + 8) | (dy + 8) << 8 | (dz + 8) << 16 | basis << 24
+    int xx = x + (d & 0xff) - 8, yy = y + ((d >> 8) & 0xff) - 8, zz = z + ((d >> 16) & 0xff) - 8;
+    xx += xx < 0 ? A.L0 : (xx >= A.L0 ? -A.L0 : 0);
+    yy += yy < 0 ? A.L1 : (yy >= A.L1 ? -A.L1 : 0);
+    zz += zz < 0 ? A.L2 : (zz >= A.L2 ? -A.L2 : 0);
+    return (d >> 24) + m * (xx + A.L0 * (yy + A.L1 * zz));
+}
+
+__device__ __forceinline__ double qsro_energy(const QsroArgs& A, int p, const uint64_t (&n)[kMaxShells])
+{
+    double acc = 0.0;
+    for (int s = 0; s < A.S; ++s) {
+        const double Zs = (double)A.Z[s];
+        for (int t = 0; t < A.K; ++t)
+            acc = acc + A.V[(s * A.K + p) * A.K + t] * ((double)(int)((n[s] >> (8 * t)) & 0xff) / Zs);
+    }
+    for (int s = 0; s < A.S; ++s) {
+        const double f = (double)(int)((n[s] >> (8 * p)) & 0xff) / (double)A.Z[s];
+        acc = acc + A.W[s * A.K + p] * (f * f);
+    }
+    return acc;
+}
+
+template <int LAT>
+__global__ __launch_bounds__(64) void k_qsro_ministep(QsroArgs A)
+{
+    constexpr int m = kGeom[LAT].m;
+    __shared__ double term[kQsroMaxAff];
+    const int lane = threadIdx.x;
+    const int ncell = A.ncx * A.ncy * A.ncz;
+    const int32_t* ox = A.org;
+    const int32_t* oy = ox + A.ncx + 1;
+    const int32_t* oz = oy + A.ncy + 1;
+    int att = 0, nacc = 0, ntie = 0;
+    for (int c = blockIdx.x; c < ncell; c += gridDim.x) {
+        const int cx = c % A.ncx, cy = (c / A.ncx) % A.ncy, cz = c / (A.ncx * A.ncy);
+        if (A.o0 >= ox[cx + 1] - ox[cx] || A.o1 >= oy[cy + 1] - oy[cy] || A.o2 >= oz[cz + 1] - oz[cz]) continue;
+        const int x = ox[cx] + A.o0, y = oy[cy] + A.o1, z = oz[cz] + A.o2;
+        const int a = A.b + m * (x + A.L0 * (y + A.L1 * z));
+        uint32_t w0, w1, w2, w3;
+        philox4x32_10((uint32_t)a, 0u, A.sweep, A.replica, (uint32_t)A.seed, (uint32_t)(A.seed >> 32), w0, w1, w2, w3);
+        (void)w3;
+        const int k = (int)__umulhi(w0, (uint32_t)A.Z1);
+        const int bsite = qsro_site_of(A, x, y, z, A.nbr[A.b * A.sumZ + k], m);
+        const int p = A.occ[a], q = A.occ[bsite];
+        ++att;
+        if (p == q) continue;
+        const int32_t* list = A.aff + (int64_t)(A.b * A.Z1 + k) * (1 + A.naff_max);
+        const int naff = list[0];
+        for (int i = lane; i < naff; i += 64) {
+            const int j = qsro_site_of(A, x, y, z, list[1 + i], m);
+            const int jb = j % m, jc = j / m;
+            const int jx = jc % A.L0, jy = (jc / A.L0) % A.L1, jz = jc / (A.L0 * A.L1);
+            const int sj = A.occ[j];
+            const int sj2 = j == a ? q : (j == bsite ? p : sj);
+            uint64_t nb[kMaxShells], na[kMaxShells];
+            const int32_t* nl = A.nbr + jb * A.sumZ;
+            int off = 0;
+            for (int s = 0; s < kMaxShells; ++s) {
+                uint64_t cb = 0, ca = 0;
+                if (s < A.S) {
+                    for (int n = 0; n < A.Z[s]; ++n) {
+                        const int xs = qsro_site_of(A, jx, jy, jz, nl[off + n], m);
+                        const int v = A.occ[xs];
+                        const int v2 = xs == a ? q : (xs == bsite ? p : v);
+                        cb += (uint64_t)1 << (8 * (v & 7));
+                        ca += (uint64_t)1 << (8 * (v2 & 7));
+                    }
+                    off += A.Z[s];
+                }
+                nb[s] = cb;
+                na[s] = ca;
+            }
+            term[i] = qsro_energy(A, min(sj2, A.K - 1), na) - qsro_energy(A, min(sj, A.K - 1), nb);
+        }
+        __syncthreads();
+        if (lane == 0) {
+            double dE = 0.0;
+            for (int i = 0; i < naff; ++i) dE = dE + term[i];
+            bool acc = true, tie = false;
+            if (!(dE <= 0.0)) {
+                const double P = exp(-(A.beta * dE));
+                const double u = (double)(((uint64_t)w1 << 21) | (uint64_t)(w2 >> 11)) * 0x1p-53;
+                acc = u < P;
+                tie = fabs(u - P) < 1e-12;
+            }
+            if (tie) {
+                ++ntie;
+                const int slot = atomicAdd(A.tie_count, 1);
+                if (slot < A.tie_cap) {
+                    smcx_tie e;
+                    e.replica = (int32_t)A.replica;
+                    e.sweep = A.sweep;
+                    e.site = a;
+                    e.decision = acc ? 1 : 0;
+                    e.pad = 0;
+                    A.ties[slot] = e;
+                }
+            }
+            if (acc) {
+                ++nacc;
+                A.occ[a] = (uint8_t)q;
+                A.occ[bsite] = (uint8_t)p;
+            }
+        }
+        __syncthreads();  // the terms are free again
+    }
+    if (lane == 0) {
+        if (att) atomicAdd((unsigned long long*)A.stats, (unsigned long long)att);
+        if (nacc) atomicAdd((unsigned long long*)(A.stats + 1), (unsigned long long)nacc);
+        if (ntie) atomicAdd((unsigned long long*)(A.stats + 2), (unsigned long long)ntie);
+    }
+}
+
+hipError_t launch_qsro_ministep(int lattice, const QsroArgs& A, int grid, hipStream_t st)
+{
+    if (lattice == SMCX_BCC)
+        hipLaunchKernelGGL(k_qsro_ministep<SMCX_BCC>, dim3((unsigned)grid), dim3(64), 0, st, A);
+    else
+        hipLaunchKernelGGL(k_qsro_ministep<SMCX_FCC>, dim3((unsigned)grid), dim3(64), 0, st, A);
+    return hipGetLastError();
+}
+
 hipError_t launch_energy(const int64_t* C, const double* V, int R, int SKK, double* E, hipStream_t st)
 {
     hipLaunchKernelGGL(k_energy, dim3((unsigned)((R + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, C, V, R, SKK, E);

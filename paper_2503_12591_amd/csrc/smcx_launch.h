@@ -22,6 +22,31 @@ hipError_t launch_advance_counter(uint32_t* counter, uint32_t n, hipStream_t st)
 hipError_t launch_pair_counts(int lattice, int K, int S, const uint8_t* occ, int64_t N, const int32_t* L,
                               int B, int64_t* counts, hipStream_t st);
 hipError_t launch_energy(const int64_t* C, const double* V, int R, int SKK, double* E, hipStream_t st);
+// Largest qSRO affected set a trial can have (entries of its LDS terms).
+constexpr int kQsroMaxAff = 256;
+
+// Arguments of one qSRO mini-step launch over one replica.
+struct QsroArgs {
+    uint8_t* occ;          // this replica's occupancy (natural layout)
+    int L0, L1, L2, K, S, Z1, sumZ, naff_max;
+    const int32_t* org;    // cell origins: x (ncx + 1), y (ncy + 1), z (ncz + 1)
+    int ncx, ncy, ncz;
+    int o0, o1, o2, b;     // the mini-step's offsets and basis site
+    uint32_t sweep, replica;
+    uint64_t seed;
+    double beta;
+    const int32_t* aff;    // [m][Z1][1 + naff_max]: count, then packed displacements
+    const int32_t* nbr;    // [m][sumZ]: packed neighbour displacements, shells in order
+    const double* V;       // [S][K][K]
+    const double* W;       // [S][K]
+    const int32_t* Z;      // [S]
+    int64_t* stats;        // this replica's attempted / accepted / near-tie counters
+    smcx_tie* ties;
+    int32_t tie_cap;
+    int32_t* tie_count;
+};
+
+hipError_t launch_qsro_ministep(int lattice, const QsroArgs& A, int grid, hipStream_t st);
 hipError_t launch_local_energy(int lattice, const uint8_t* occ, const int32_t* L, int K, int S, const double* V,
                                double* e, hipStream_t st);
 hipError_t launch_clusters(int lattice, const double* e, const int32_t* L, double threshold, int32_t* label,

@@ -30,6 +30,7 @@ EXPORTS = [
     "smcx_sweep_capture",
     "smcx_graph_launch", "smcx_graph_destroy", "smcx_timing_enable", "smcx_timing_read",
     "smcx_energy_dev", "smcx_exchange", "smcx_anneal", "smcx_local_energy", "smcx_clusters",
+    "smcx_set_qsro", "smcx_sweep_qsro",
 ]
 
 
@@ -82,6 +83,8 @@ def lib():
     L.smcx_anneal.argtypes = [p, i32, i32, i32, u64, u32, p, p, p, p, p, p, i32, p, i32, p]
     L.smcx_local_energy.argtypes = [p, i32, p, p]
     L.smcx_clusters.argtypes = [p, i32, p, C.c_double, p, p, p, p]
+    L.smcx_set_qsro.argtypes = [p, p, p, p]
+    L.smcx_sweep_qsro.argtypes = [p, i32, u64, u32, p, p, p, i32, p, p]
     _lib = L
     return L
 
@@ -231,6 +234,30 @@ class Lattice:
                                 _ptr(stats), _ptr(ties), tie_cap, _ptr(tie_count), mode,
                                 _stream(torch)))
         self._last_beta = b  # keep alive until the stream has consumed it
+        return stats, ties, tie_count
+
+    def set_qsro(self, V, W):
+        """qSRO model parameters: V [S][K][K] (symmetric), W [S][K]."""
+        V = np.ascontiguousarray(np.asarray(V, dtype=np.float64).reshape(self.S, self.K, self.K))
+        W = np.ascontiguousarray(np.asarray(W, dtype=np.float64).reshape(self.S, self.K))
+        _check(lib().smcx_set_qsro(self.h, V.ctypes.data_as(C.c_void_p), W.ctypes.data_as(C.c_void_p),
+                                   _stream(self.torch)))
+
+    def sweep_qsro(self, n_sweeps: int, seed: int, betas, first_sweep: int = 0, tie_cap: int = 4096,
+                   stats=None, ties=None, tie_count=None):
+        """n_sweeps sweeps under the qSRO model; betas [n_sweeps][R] (host)."""
+        torch = self.torch
+        b = np.ascontiguousarray(np.broadcast_to(np.asarray(betas, np.float64).reshape(n_sweeps, -1),
+                                                 (n_sweeps, self.R)))
+        if stats is None:
+            stats = torch.zeros(self.R * 3, dtype=torch.int64, device="cuda")
+        if ties is None:
+            ties = torch.zeros(max(tie_cap, 1) * TIE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        if tie_count is None:
+            tie_count = torch.zeros(1, dtype=torch.int32, device="cuda")
+        _check(lib().smcx_sweep_qsro(self.h, n_sweeps, C.c_uint64(seed), C.c_uint32(first_sweep),
+                                     b.ctypes.data_as(C.c_void_p), _ptr(stats), _ptr(ties), tie_cap,
+                                     _ptr(tie_count), _stream(torch)))
         return stats, ties, tie_count
 
     def sweep_partial(self, sweep: int, tau_begin: int, tau_end: int, seed: int, betas, mode="auto",
