@@ -227,6 +227,8 @@ def main():
         out["tempering"] = tempering_bench(args)
         print("[bench] anneal", file=sys.stderr, flush=True)
         out["anneal"] = anneal_bench(args)
+        print("[bench] qsro", file=sys.stderr, flush=True)
+        out["qsro"] = qsro_bench(args)
     if not args.no_ladder:
         print("[bench] clusters", file=sys.stderr, flush=True)
         out["clusters"] = clusters_bench(lat, N)
@@ -434,6 +436,42 @@ def clusters_bench(lat, N):
            "largest": int(size.max().item())}
     del e, label, size
     return out
+
+
+def qsro_bench(args, sweeps: int = 2):
+    """The qSRO model on FCC 64^3 (5 species, 2 shells, 1000 K, link cells of
+    4, the interaction-zone minimum): attempted swaps/s of qSRO sweeps
+    (smcx_sweep_qsro: a wave per trial over its affected set) beside EPI
+    sweeps of the same lattice and partition; their ratio is the cost of
+    the nonlinear model per trial."""
+    import torch
+    from paper_2503_12591_amd import inputs as I
+    from paper_2503_12591_amd import smcx
+    dims, counts, V, W, beta = I.qsro_fcc()
+    occ = I.occupancy(counts, seed=0)
+    N = len(occ)
+    lat = smcx.Lattice(I.FCC, dims, 5, 2, occ, ell=4)
+    lat.set_qsro(V, W)
+    lat.set_epi(V)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    lat.sweep_qsro(1, 0, [beta])  # warm-up
+    tq = timed(lambda: lat.sweep_qsro(sweeps, 0, [beta] * sweeps, first_sweep=1))
+    bt = np.full((sweeps, 1), beta)
+    lat.sweep(1, 0, bt[:1], first_sweep=1 + sweeps)
+    te = timed(lambda: lat.sweep(sweeps, 0, bt, first_sweep=2 + sweeps))
+    lat.close()
+    return {"workload": "fcc64_k5_s2_T1000_qsro", "sites": N, "sweeps": sweeps, "unit": "attempted swaps/s",
+            "qsro_swaps_per_s": sweeps * N / tq, "epi_swaps_per_s_same_lattice": sweeps * N / te,
+            "qsro_cost_over_epi": te and tq / te}
 
 
 def algorithmic_bytes_per_launch(cells, N, m, launches_per_sweep):

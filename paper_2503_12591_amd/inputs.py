@@ -206,6 +206,19 @@ def c4a_ladder(R: int = 256, n_sweeps: int = 1000, lo: int = 16, hi: int = 48) -
     return Ladder(edges.astype(np.int32), 4, 4, epi(4, 4, 0.02, seed=4), beta_of_T(T), n_sweeps)
 
 
+def qsro_fcc(edge: int = 64):
+    """FCC edge^3 (1,048,576 sites at 64), 5 species 0.28/0.28/0.28/0.08/0.08,
+    2 shells, 1000 K: shaped like the paper's one-million-atom FeCoNiAlTi
+    runs with its qSRO model.  Returns (dims, counts, V [2][5][5],
+    W [2][5], beta)."""
+    dims = (edge, edge, edge)
+    N = n_sites(FCC, dims)
+    counts = composition([0.28, 0.28, 0.28, 0.08, 0.08], N)
+    V = epi(5, 2, 0.03, seed=3)
+    W = rng(9).normal(0.0, 0.05, (2, 5))
+    return dims, counts, V, W, float(beta_of_T(1000.0))
+
+
 def tempering_ladder(R: int = 256, edge: int = 32, n_sweeps: int = 1000) -> Ladder:
     """R cubic BCC replicas of one edge for replica exchange (the ladder's
     temperatures and EPI; the edge is the mean of its 16..48 range)."""
