@@ -229,6 +229,10 @@ def main():
         out["anneal"] = anneal_bench(args)
         print("[bench] qsro", file=sys.stderr, flush=True)
         out["qsro"] = qsro_bench(args)
+        print("[bench] fcc128", file=sys.stderr, flush=True)
+        out["fcc128"] = fcc128_bench(args)
+        print("[bench] backward", file=sys.stderr, flush=True)
+        out["backward"] = backward_bench(args)
     if not args.no_ladder:
         print("[bench] clusters", file=sys.stderr, flush=True)
         out["clusters"] = clusters_bench(lat, N)
@@ -472,6 +476,62 @@ def qsro_bench(args, sweeps: int = 2):
     return {"workload": "fcc64_k5_s2_T1000_qsro", "sites": N, "sweeps": sweeps, "unit": "attempted swaps/s",
             "qsro_swaps_per_s": sweeps * N / tq, "epi_swaps_per_s_same_lattice": sweeps * N / te,
             "qsro_cost_over_epi": te and tq / te}
+
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    r = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3, r
+
+
+def fcc128_bench(args, sweeps: int = 10):
+    """FCC 128^3 (8.4e6 sites, 5 species 0.28/0.28/0.28/0.08/0.08, 4 shells,
+    800 K): attempted swaps/s of 10 sweeps followed by the energy and SRO
+    measurement the workload takes every 10 sweeps."""
+    import torch
+    from paper_2503_12591_amd import inputs as I
+    from paper_2503_12591_amd import smcx
+    w = I.c3_fcc()
+    lat = smcx.Lattice(w.lattice, w.dims, w.K, w.S, w.occ(), ell=4)
+    lat.set_epi(w.V)
+    bt = w.betas[:sweeps].reshape(-1, 1)
+    lat.sweep(1, 0, bt[:1])
+    lat.sro()
+
+    def step():
+        lat.sweep(sweeps, 0, bt, first_sweep=1)
+        return lat.sro()
+
+    secs, _ = _timed(step)
+    lat.close()
+    return {"workload": w.name, "sites": w.N, "sweeps": sweeps, "unit": "attempted swaps/s",
+            "swaps_per_s": sweeps * w.N / secs, "ms": secs * 1e3}
+
+
+def backward_bench(args):
+    """energy_backward (batched pair counts, dE/dV = C / 2) at the workloads'
+    batch sizes: 64 snapshots of BCC 64^3 (3.4e7 sites) and 4096
+    configurations of BCC 16^3 (the fit set, 3.4e7 sites); one byte per site
+    read, so the rate is in sites/s and GB/s."""
+    import torch
+    from paper_2503_12591_amd import inputs as I
+    from paper_2503_12591_amd import smcx
+    out = {"unit": "sites/s"}
+    for name, dims, B in (("bcc64_snapshots64", (64, 64, 64), 64), ("bcc16_fit4096", (16, 16, 16), 4096)):
+        N = I.n_sites(I.BCC, dims)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(7)
+        batch = torch.randint(0, 4, (B, N), dtype=torch.uint8, device="cuda", generator=g)
+        smcx.energy_backward_counts(I.BCC, dims, 4, 4, batch)  # warm-up
+        secs, _ = _timed(lambda: smcx.energy_backward_counts(I.BCC, dims, 4, 4, batch))
+        out[name] = {"sites": B * N, "ms": secs * 1e3, "sites_per_s": B * N / secs, "GBps": B * N / secs / 1e9}
+        del batch
+    return out
 
 
 def algorithmic_bytes_per_launch(cells, N, m, launches_per_sweep):
