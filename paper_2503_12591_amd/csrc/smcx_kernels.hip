@@ -1804,6 +1804,81 @@ __global__ __launch_bounds__(kBlock) void k_local_energy(const uint8_t* occ, int
         local_energy_sites<LAT, 0>(occ, c, L0, L1, L2, K, S, Vs, e);
 }
 
+// Local energies for K <= 4 from LDS tiles, the layout of
+// k_pair_counts_tiled: TX x (256 / TX) lanes over x and y, 16 sites deep in
+// z, the tile plus a 2-cell halo staged once; a shell's neighbours are
+// counted into 8-bit fields of one word (offsets fixed at compile time) and
+// e is formed in the order of k_local_energy (s, then t).
+template <int LAT, int TX>
+__global__ __launch_bounds__(kBlock) void k_local_energy_tiled(const uint8_t* occ, int L0, int L1, int L2, int K,
+                                                               int S, const double* V, double* e)
+{
+    constexpr Geometry G = kGeom[LAT];
+    constexpr int m = G.m;
+    constexpr int TY = kBlock / TX, TZ = 16;
+    constexpr int WX = TX + 2 * kHalo, WY = TY + 2 * kHalo, WZ = TZ + 2 * kHalo;
+    constexpr int LP = WX * m, PL = LP * WY;
+    __shared__ __align__(16) uint8_t win[PL * WZ];
+    __shared__ double Vs[kMaxShells * 4 * 4];
+    for (int i = threadIdx.x; i < S * K * K; i += blockDim.x) Vs[i] = V[i];
+    const int ntx = (L0 + TX - 1) / TX, nty = (L1 + TY - 1) / TY, ntz = (L2 + TZ - 1) / TZ;
+    const int64_t ntiles = (int64_t)ntx * nty * ntz;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    auto wrap = [](int v, int L) {
+        v += v < 0 ? L : 0;
+        v -= v >= L ? L : 0;
+        return v >= L ? v % L : v;  // only lattices narrower than a tile wrap twice
+    };
+    for (int64_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+        const int tx = (int)(ti % ntx);
+        const int64_t tr = ti / ntx;
+        const int ty = (int)(tr % nty), tz = (int)(tr / nty);
+        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+        __syncthreads();  // every lane is done with the previous tile (and Vs is in place)
+        for (int c = threadIdx.x; c < WX * WY * WZ; c += blockDim.x) {
+            const int wx = c % WX, wr = c / WX, wy = wr % WY, wz = wr / WY;
+            const int x = wrap(x0 + wx - kHalo, L0), y = wrap(y0 + wy - kHalo, L1), z = wrap(z0 + wz - kHalo, L2);
+            const int64_t cell = x + (int64_t)L0 * (y + (int64_t)L1 * z);
+            uint8_t* d = win + (wz * WY + wy) * LP + wx * m;
+            if constexpr (m == 2) *(uint16_t*)d = *(const uint16_t*)(occ + 2 * cell);
+            else *(uint32_t*)d = *(const uint32_t*)(occ + 4 * cell);
+        }
+        __syncthreads();
+        if (x0 + lx >= L0 || y0 + ly >= L1) continue;
+        for (int lz = 0; lz < TZ && z0 + lz < L2; ++lz) {
+            const int64_t cell = (x0 + lx) + (int64_t)L0 * ((y0 + ly) + (int64_t)L1 * (z0 + lz));
+#pragma unroll
+            for (int b = 0; b < m; ++b) {
+                const int base = ((lz + kHalo) * WY + (ly + kHalo)) * LP + (lx + kHalo) * m + b;
+                const int p = min((int)win[base], K - 1);  // checked < K at init
+                uint32_t h[kMaxShells];
+#pragma unroll
+                for (int s = 0; s < kMaxShells; ++s) {
+                    uint32_t a = 0;
+                    if (s < S) {
+                        uint32_t v[kMaxZ];
+#pragma unroll
+                        for (int n = 0; n < G.Z[s]; ++n) {
+                            const Nb nb = nb_of(G, b, G.v[s][n][0], G.v[s][n][1], G.v[s][n][2]);
+                            v[n] = win[base + nb.dz * PL + nb.dy * LP + m * nb.dx + (nb.bt - b)];
+                        }
+#pragma unroll
+                        for (int n = 0; n < G.Z[s]; ++n) a += 1u << (8 * (v[n] & 3u));
+                    }
+                    h[s] = a;
+                }
+                double en = 0.0;
+#pragma unroll
+                for (int s = 0; s < kMaxShells; ++s)
+                    if (s < S)
+                        for (int t = 0; t < K; ++t)
+                            en = en + (double)(int)((h[s] >> (8 * t)) & 0xff) * Vs[(s * K + p) * K + t];
+                e[b + m * cell] = 0.5 * en;
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ int32_t par_load(const int32_t* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1913,6 +1988,19 @@ hipError_t launch_local_energy(int lattice, const uint8_t* occ, const int32_t* L
                                double* e, hipStream_t st)
 {
     const int64_t ncell = (int64_t)L[0] * L[1] * L[2];
+    if (K <= 4) {
+        const bool wide = L[0] >= 48;
+        const int TX = wide ? 64 : 16, TY = kBlock / TX;
+        const int64_t ntiles = (int64_t)((L[0] + TX - 1) / TX) * ((L[1] + TY - 1) / TY) * ((L[2] + 15) / 16);
+        const unsigned g = (unsigned)std::min<int64_t>(ntiles, 1 << 20);
+        auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, occ, L[0], L[1], L[2], K, S, V, e); };
+        if (lattice == SMCX_BCC) {
+            if (wide) go(k_local_energy_tiled<SMCX_BCC, 64>); else go(k_local_energy_tiled<SMCX_BCC, 16>);
+        } else {
+            if (wide) go(k_local_energy_tiled<SMCX_FCC, 64>); else go(k_local_energy_tiled<SMCX_FCC, 16>);
+        }
+        return hipGetLastError();
+    }
     const unsigned nb = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (ncell + kBlock - 1) / kBlock), 1 << 20);
     if (lattice == SMCX_BCC)
         hipLaunchKernelGGL(k_local_energy<SMCX_BCC>, dim3(nb), dim3(kBlock), 0, st, occ, L[0], L[1], L[2], K, S, V, e);
