@@ -100,7 +100,7 @@ struct Plan {
     LdsLayout lds;
     size_t off_reps, off_origins, off_tileoff, off_offP, off_offB, off_pd, off_D, off_V, off_misc, off_pad, total;
     // qSRO model: affected-set and neighbour tables, V, W, Z
-    size_t off_qaff, off_qnbr, off_qV, off_qW, off_qZ;
+    size_t off_qaff, off_qnbr, off_qV, off_qW, off_qZ, off_qslots;
     int qnaff;  // largest affected set
     int n_origins;
     int64_t total_sites, total_tiles;
@@ -389,6 +389,7 @@ int make_plan(const smcx_desc* d, Plan& P)
     P.off_qV = o; o = align256(o + sizeof(double) * P.S * P.K * P.K);
     P.off_qW = o; o = align256(o + sizeof(double) * P.S * P.K);
     P.off_qZ = o; o = align256(o + sizeof(int32_t) * kMaxShells);
+    P.off_qslots = o; o = align256(o + sizeof(int64_t) * 3 * kQsroGrid);
     P.off_rowoff = o; o = align256(o + sizeof(int64_t) * (P.R + 1));
     P.off_offP_r = o; o = align256(o + sizeof(int16_t) * P.m * P.Z1 * P.sumZ);
     P.off_offB_r = o; o = align256(o + sizeof(int32_t) * P.m * P.Z1);
@@ -888,12 +889,13 @@ int smcx_sweep_qsro(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t f
             A.V = (const double*)(h->ws + P.off_qV);
             A.W = (const double*)(h->ws + P.off_qW);
             A.Z = (const int32_t*)(h->ws + P.off_qZ);
-            A.stats = stats_dev + 3 * (int64_t)r;
+            A.slots = (int64_t*)(h->ws + P.off_qslots);
             A.ties = ties_dev;
             A.tie_cap = tie_cap;
             A.tie_count = tie_count_dev;
             const int ncell = A.ncx * A.ncy * A.ncz;
-            const int grid = std::min(ncell, 8192);
+            const int grid = std::min(ncell, kQsroGrid);
+            SMCX_HIP(launch_fill_i64(A.slots, 3 * (int64_t)grid, 0, st));
             for (int tau = 0; tau < R.nA; ++tau) {
                 A.b = tau % P.m;
                 const int rest = tau / P.m;
@@ -902,6 +904,7 @@ int smcx_sweep_qsro(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t f
                 A.o2 = rest / (R.M[0] * R.M[1]);
                 SMCX_HIP(launch_qsro_ministep(P.lattice, A, grid, st));
             }
+            SMCX_HIP(launch_qsro_reduce(A.slots, grid, stats_dev + 3 * (int64_t)r, st));
         }
     return SMCX_OK;
 }

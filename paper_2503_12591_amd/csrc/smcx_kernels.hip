@@ -2153,10 +2153,39 @@ __global__ __launch_bounds__(64) void k_qsro_ministep(QsroArgs A)
         __syncthreads();  // the terms are free again
     }
     if (lane == 0) {
-        if (att) atomicAdd((unsigned long long*)A.stats, (unsigned long long)att);
-        if (nacc) atomicAdd((unsigned long long*)(A.stats + 1), (unsigned long long)nacc);
-        if (ntie) atomicAdd((unsigned long long*)(A.stats + 2), (unsigned long long)ntie);
+        // this workgroup's own counter slot (no other workgroup of the
+        // launch writes it; launches on one stream follow each other), so no
+        // atomics: thousands of atomics on one address would serialise
+        int64_t* slot = A.slots + 3 * (int64_t)blockIdx.x;
+        slot[0] += att;
+        slot[1] += nacc;
+        slot[2] += ntie;
     }
+}
+
+// Sum the workgroups' counter slots into a replica's counters.
+__global__ void k_qsro_reduce(const int64_t* slots, int n, int64_t* stats)
+{
+    int64_t v[3] = {0, 0, 0};
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        for (int c = 0; c < 3; ++c) v[c] += slots[3 * (int64_t)i + c];
+    __shared__ int64_t red[3][kBlock];
+    for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c)
+            if (red[c][0]) atomicAdd((unsigned long long*)(stats + c), (unsigned long long)red[c][0]);
+}
+
+hipError_t launch_qsro_reduce(const int64_t* slots, int n, int64_t* stats, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_qsro_reduce, dim3(1), dim3(kBlock), 0, st, slots, n, stats);
+    return hipGetLastError();
 }
 
 hipError_t launch_qsro_ministep(int lattice, const QsroArgs& A, int grid, hipStream_t st)

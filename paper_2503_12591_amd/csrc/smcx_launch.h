@@ -40,13 +40,16 @@ struct QsroArgs {
     const double* V;       // [S][K][K]
     const double* W;       // [S][K]
     const int32_t* Z;      // [S]
-    int64_t* stats;        // this replica's attempted / accepted / near-tie counters
+    int64_t* slots;        // [gridDim][3]: each workgroup's attempted / accepted / near-tie counts
     smcx_tie* ties;
     int32_t tie_cap;
     int32_t* tie_count;
 };
 
 hipError_t launch_qsro_ministep(int lattice, const QsroArgs& A, int grid, hipStream_t st);
+hipError_t launch_qsro_reduce(const int64_t* slots, int n, int64_t* stats, hipStream_t st);
+// workgroups of a qSRO mini-step launch (each has a counter slot)
+constexpr int kQsroGrid = 8192;
 hipError_t launch_local_energy(int lattice, const uint8_t* occ, const int32_t* L, int K, int S, const double* V,
                                double* e, hipStream_t st);
 hipError_t launch_clusters(int lattice, const double* e, const int32_t* L, double threshold, int32_t* label,
