@@ -355,9 +355,14 @@ int make_plan(const smcx_desc* d, Plan& P)
             P.rWZ = best[3];
             P.rlds = lds_layout(P.lattice, P.K, P.S, P.Z1, P.sumZ, best_win, 1);
             P.row_preset = -1;
+            // presets assume no partner has images in other shells
+            bool images = false;
+            for (const Replica& R : P.reps)
+                for (int s = 0; s < kMaxShells; ++s)
+                    for (int k = 0; k < P.Z1; ++k) images |= R.mult[s][k] != (s == 0 ? 1 : 0);
             for (int pi = 0; pi < kNumRowPresets; ++pi) {
                 const RowPreset& q = kRowPresets[pi];
-                if (same_cp && q.lattice == P.lattice && q.K == P.K && q.S == P.S && q.cp == P.reps[0].cp && q.LP == P.rLP &&
+                if (same_cp && !images && q.lattice == P.lattice && q.K == P.K && q.S == P.S && q.cp == P.reps[0].cp && q.LP == P.rLP &&
                     q.WY == P.rWY && q.WZ == P.rWZ && q.rt0 == P.RT[0] && q.rt1 == P.RT[1] && q.rt2 == P.RT[2])
                     P.row_preset = pi;
             }

@@ -46,8 +46,13 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        // round 0: words 1 and 3 are often wave-uniform, so their xor with
+        // the key is left to scalar code; later rounds take one three-input
+        // xor (truth table 0x96) instead of two xors
+        const uint32_t n0 = r == 0 ? (uint32_t)(p1 >> 32) ^ (c1 ^ k0)
+                                   : __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = r == 0 ? (uint32_t)(p0 >> 32) ^ (c3 ^ k1)
+                                   : __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -299,6 +304,7 @@ struct GeoRt {
     static constexpr bool fixed = false;
     static constexpr bool rows = false;
     static constexpr bool own_cp = false;
+    static constexpr bool may_alias = true;  // a partner may have images in other shells (an edge of 2)
     static constexpr int ELL = 0;
     __device__ static int T(const SweepArgs& A, int a) { return A.T[a]; }
     __device__ static int LP(const SweepArgs& A) { return A.LP; }
@@ -317,6 +323,7 @@ struct GeoFix {
     static constexpr bool fixed = true;
     static constexpr bool rows = false;
     static constexpr bool own_cp = false;
+    static constexpr bool may_alias = true;
     static constexpr int ELL = P.ell;
     static constexpr int kLP = preset_LP(P), kWY = preset_WY(P), kWZ = preset_WZ(P);
     static constexpr int kBLOCK = (P.tx * P.ty * P.tz + 63) / 64 * 64;
@@ -347,6 +354,7 @@ template <int PI>
 struct GeoRowFix : GeoRt {
     static constexpr RowPreset P = kRowPresets[PI];
     static constexpr bool rows = true;
+    static constexpr bool may_alias = false;  // chosen only for lattices without partner images
     __device__ static constexpr int T(const SweepArgs&, int a) { return a == 0 ? P.rt0 : (a == 1 ? P.rt1 : P.rt2); }
     __device__ static constexpr int LP(const SweepArgs&) { return P.LP; }
     __device__ static constexpr int WY(const SweepArgs&) { return P.WY; }
@@ -414,47 +422,81 @@ __device__ __forceinline__ bool tile_geometry(const SweepArgs& A, const RepDev& 
 }
 
 // Issue the window loads of a tile straight into LDS (global_load_lds_dwordx4:
-// lane i of a wave writes the 16 bytes at M0 + 16 i).  Window slot j (16
-// bytes at buf + 16 j) is row R = j / LPc, chunk j % LPc; row R holds window
-// plane R / WY, row R % WY.  The loads complete asynchronously; the caller
-// waits on vmcnt and a barrier before reading the buffer.
+// lane i of a wave writes the 16 bytes at M0 + 16 i).  Window row R (plane
+// R / WY, row R % WY) occupies LP bytes at buf + R LP.  Long rows go a wave
+// per row (R = wave, wave + waves, ...): the row's source address is
+// wave-uniform and a lane's part of it 16 bytes per chunk.  Short rows would
+// leave most lanes of such a wave idle, so there window slot j (16 bytes at
+// buf + 16 j: row j / (LP / 16), chunk j % (LP / 16)) goes to thread j, j +
+// block, ..., each advancing its source address by fixed steps.  Blocks are
+// whole waves.  The loads complete asynchronously; the caller waits on vmcnt
+// and a barrier before reading the buffer.
 template <int LAT, class Geo>
 __device__ __forceinline__ void stage_async(const SweepArgs& A, const RepDev& rep, const TileGeom& tg,
                                             const uint8_t* pad, uint8_t* buf)
 {
     constexpr int m = kGeom[LAT].m;
-    const int LPc = Geo::LP(A) >> 4;
+    const int LP = Geo::LP(A), LPc = LP >> 4;
     const int WY = Geo::WY(A);
-    const int nslots = Geo::WZ(A) * WY * LPc;
+    const int nrows = Geo::WZ(A) * WY;
     // row windows hold whole basis-planar rows; tile windows a byte range of
     // interleaved rows
     const int grow = Geo::rows ? rep.prowp : rep.prow;
     const int gx1 = Geo::rows ? rep.prowp : (m * (tg.w0[0] + tg.n[0] + kHalo) + 15) & ~15;
-    const int n16 = (gx1 - tg.gx0) >> 4;
+    const int n16 = min((gx1 - tg.gx0) >> 4, LPc);  // chunks of a row, never past the window's pitch
+    // the window geometry is the same in every lane: scalar registers keep
+    // the loops and the row addresses out of vector code
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int step = Geo::block(A);
+    const int block = __builtin_amdgcn_readfirstlane(Geo::block(A));
+    const int n1 = __builtin_amdgcn_readfirstlane(tg.n[1]), n2 = __builtin_amdgcn_readfirstlane(tg.n[2]);
+    const uint64_t off = (uint64_t)(((int64_t)(tg.w0[2] + kHalo) * rep.prows + (tg.w0[1] + kHalo)) * grow + tg.gx0);
+    const uint8_t* base = pad + (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(off >> 32)) << 32) |
+                                          __builtin_amdgcn_readfirstlane((uint32_t)off));
+    const int64_t plane = (int64_t)rep.prows * grow;
+    if (n16 >= 40) {
+        const int nwaves = block >> 6;
+        int wz = wave / WY, wy = wave - wz * WY;
+        for (int R = wave; R < nrows; R += nwaves) {
+            if (wy < n1 && wz < n2) {
+                const uint8_t* row = base + wz * plane + (int64_t)wy * grow;
+                for (int cb = 0; cb < n16; cb += 64)
+                    if (cb + lane < n16)
+                        __builtin_amdgcn_global_load_lds(
+                            (const __attribute__((address_space(1))) void*)(row + 16 * (cb + lane)),
+                            (__attribute__((address_space(3))) void*)(buf + R * LP + 16 * cb), 16, 0, 0);
+            }
+            wy += nwaves;
+            while (wy >= WY) {
+                wy -= WY;
+                ++wz;
+            }
+        }
+        return;
+    }
+    const int nslots = nrows * LPc;
     int j = wave * 64 + lane;
     int R = j / LPc, col = j - R * LPc;
     int wz = R / WY, wy = R - wz * WY;
-    const int dR = step / LPc, dcol = step - dR * LPc;
-    const uint8_t* base = pad + ((int64_t)(tg.w0[2] + kHalo) * rep.prows + (tg.w0[1] + kHalo)) * grow + tg.gx0;
-    const int64_t plane = (int64_t)rep.prows * grow;
-    for (int jb = wave * 64; jb < nslots; jb += step) {
-        if (jb + lane < nslots && col < n16 && wy < tg.n[1] && wz < tg.n[2]) {
-            const uint8_t* src = base + wz * plane + (int64_t)wy * grow + 16 * col;
+    const int dR = block / LPc, dcol = block - dR * LPc;
+    const uint8_t* src = base + wz * plane + (int64_t)wy * grow + 16 * col;
+    const int64_t step = (int64_t)dR * grow + 16 * dcol, wrap_col = grow - 16 * LPc, wrap_row = plane - (int64_t)WY * grow;
+    for (int jb = wave * 64; jb < nslots; jb += block) {
+        if (jb + lane < nslots && col < n16 && wy < n1 && wz < n2)
             __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
                                              (__attribute__((address_space(3))) void*)(buf + 16 * jb), 16, 0, 0);
-        }
         col += dcol;
         wy += dR;
+        src += step;
         if (col >= LPc) {
             col -= LPc;
             ++wy;
+            src += wrap_col;
         }
         while (wy >= WY) {
             wy -= WY;
             ++wz;
+            src += wrap_row;
         }
     }
 }
@@ -589,18 +631,21 @@ __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& re
     // D[s][t][p][q]: the lanes' (p, q) entries of one term lie in one
     // K*K*8-byte block, so their reads do not collide in LDS banks
     const double* Dp = T.D + (p * K + q);
-    double dE = 0.0;
+    // the sum starts from the first product rather than from +0.0 + it: the
+    // two differ only in the sign of a zero sum, and dE <= 0 accepts either
+    double dE;
 #pragma unroll
     for (int s = 0; s < kMaxShells; ++s) {
         if (s < S) {
             // images of the partner inside shell s (1, 0, 0, 0 unless an edge is 2)
-            const CT mu = rep.alias ? (CT)rep.mult[s][k] : (CT)(s == 0 ? 1 : 0);
+            const CT mu = Geo::may_alias && rep.alias ? (CT)rep.mult[s][k] : (CT)(s == 0 ? 1 : 0);
             const CT d = L.Ca[s] + EN::bias - L.Cb[s] + (mu << p8) - (mu << q8);
 #pragma unroll
             for (int tt = 0; tt < EN::KP; ++tt) {
                 if (tt < K) {
                     const int c = (int)((d >> (EN::F * tt)) & EN::mask) - EN::half;
-                    dE = dE + (double)c * Dp[(s * K + tt) * K * K];
+                    const double term = (double)c * Dp[(s * K + tt) * K * K];
+                    dE = s == 0 && tt == 0 ? term : dE + term;
                 }
             }
         }
@@ -1040,31 +1085,40 @@ __device__ __forceinline__ void rows_writeback(const SweepArgs& A, const RepDev&
 {
     constexpr Geometry G = kGeom[LAT];
     constexpr int PLO = partner_reach(G, false), NP = partner_reach(G, true) - PLO + 1;
+    constexpr int NR = NP * NP;  // candidate rows: partners reach NP rows along y and along z
     const int LP = Geo::LP(A), WY = Geo::WY(A);
     const int n16 = rep.prowp >> 4;
-    const int items = NP * NP * n16;
     const int Ly = rep.L[1], Lz = rep.L[2];
     const int64_t prowp = rep.prowp, plane = (int64_t)rep.prows * prowp;
-    // item k: row d = k / n16 of the NP x NP candidates, chunk c = k % n16
-    int d = lx / n16, c = lx - d * n16;
-    const int dd = T0 / n16, dc = T0 - dd * n16;
-    for (int k = lx; k < items; k += T0) {
+    // g lanes per row, consecutive lanes on consecutive 16-byte chunks of one
+    // row, so the row's addresses are worked out once per lane; with fewer
+    // lanes than rows a lane takes rows lx, lx + T0, ...
+    const int g = T0 / NR;
+    int d = lx, dstep = T0, c0 = 0, cstep = 1;
+    if (g > 0) {
+        if (lx >= g * NR) return;
+        d = lx / g;
+        dstep = NR;
+        c0 = lx - d * g;
+        cstep = g;
+    }
+    for (; d < NR; d += dstep) {
         const int y = ya + d % NP + PLO, z = za + d / NP + PLO;  // in [-1, L]
-        const uint4 v = *(const uint4*)(win + ((z - tg.w0[2]) * WY + (y - tg.w0[1])) * LP + 16 * c);
         const int yr = y < 0 ? y + Ly : (y >= Ly ? y - Ly : y);
         const int zr = z < 0 ? z + Lz : (z >= Lz ? z - Lz : z);
         const int yi = yr < kHalo ? yr + Ly : (yr >= Ly - kHalo ? yr - Ly : yr);  // image, or yr itself
         const int zi = zr < kHalo ? zr + Lz : (zr >= Lz - kHalo ? zr - Lz : zr);
-        uint8_t* col = pad + 16 * c;
-        *(uint4*)(col + (zr + kHalo) * plane + (yr + kHalo) * prowp) = v;
-        if (yi != yr) *(uint4*)(col + (zr + kHalo) * plane + (yi + kHalo) * prowp) = v;
-        if (zi != zr) *(uint4*)(col + (zi + kHalo) * plane + (yr + kHalo) * prowp) = v;
-        if (yi != yr && zi != zr) *(uint4*)(col + (zi + kHalo) * plane + (yi + kHalo) * prowp) = v;
-        c += dc;
-        d += dd;
-        if (c >= n16) {
-            c -= n16;
-            ++d;
+        const uint8_t* src = win + ((z - tg.w0[2]) * WY + (y - tg.w0[1])) * LP + 16 * c0;
+        uint8_t* dst = pad + (zr + kHalo) * plane + (yr + kHalo) * prowp + 16 * c0;
+        const int64_t dy = (int64_t)(yi - yr) * prowp, dz = (int64_t)(zi - zr) * plane;  // images (0: none)
+        for (int c = c0; c < n16; c += cstep) {
+            const uint4 v = *(const uint4*)src;
+            *(uint4*)dst = v;
+            if (dy) *(uint4*)(dst + dy) = v;
+            if (dz) *(uint4*)(dst + dz) = v;
+            if (dy && dz) *(uint4*)(dst + dy + dz) = v;
+            src += 16 * cstep;
+            dst += 16 * cstep;
         }
     }
 }
