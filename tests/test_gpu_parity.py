@@ -129,6 +129,9 @@ def test_trajectories_varied_geometry(smcx, lattice, dims, K, S, ell, tile, mode
     (FCC, (9, 8, 10), 5, 4, 3),       # 6-bit counters
     (BCC, (12, 9, 10), 4, 2, 3),      # two shells
     (FCC, (12, 12, 12), 3, 3, 4),
+    (BCC, (332, 8, 8), 4, 4, 4),      # long padded rows: a wave per window row when staging
+    (BCC, (327, 9, 8), 4, 4, 4),      # long rows, uneven cells
+    (FCC, (170, 6, 6), 5, 4, 4),      # long FCC rows, 6-bit counters
 ])
 def test_stream_rows_and_tiles(smcx, lattice, dims, K, S, ell, rows):
     """Stream mode with whole-row windows (all offsets o_x of a group in one
