@@ -561,7 +561,7 @@ struct LaneState {
 template <int LAT, int E, int B, class Geo>
 __device__ __forceinline__ void trial_read(const SweepArgs& A, const RepDev& rep, const Lds& T, const uint8_t* win,
                                            const TileGeom& tg, int r, uint32_t t, int ax, int ay, int az,
-                                           LaneState<E>& L)
+                                           LaneState<E>& L, int64_t yz = 0)
 {
     using CT = typename Enc<E>::T;
     constexpr Geometry G = kGeom[LAT];
@@ -572,7 +572,13 @@ __device__ __forceinline__ void trial_read(const SweepArgs& A, const RepDev& rep
     constexpr bool PLANAR = Geo::rows;
     const int la = ((az - tg.w0[2]) * WY + (ay - tg.w0[1])) * LP +
                    (PLANAR ? B * Geo::CP(rep) + ax + kHalo : m * (ax + kHalo) + B) - tg.gx0;
-    const int64_t ia = B + (int64_t)m * (ax + (int64_t)rep.L[0] * (ay + (int64_t)rep.L[1] * az));
+    // site index b + m (x + L0 (y + L1 z)); row kernels pass yz = m L0 (y + L1 z),
+    // fixed for a row group, so a trial adds only b + m x
+    int64_t ia;
+    if constexpr (Geo::rows)
+        ia = yz + (B + m * ax);
+    else
+        ia = B + (int64_t)m * (ax + (int64_t)rep.L[0] * (ay + (int64_t)rep.L[1] * az));
     uint32_t w0, w1, w2, w3;
     philox4x32_10((uint32_t)ia, (uint32_t)((uint64_t)ia >> 32), t, (uint32_t)r, (uint32_t)A.seed,
                   (uint32_t)(A.seed >> 32), w0, w1, w2, w3);
@@ -1058,15 +1064,15 @@ __global__ __launch_bounds__(kBlock) void k_ministep(SweepArgs A)
 template <int LAT, int E, class Geo, int B>
 __device__ __forceinline__ void row_trials(int b0, int b1, const SweepArgs& A, const RepDev& rep, const Lds& T,
                                            uint8_t* win, const TileGeom& tg, int r, uint32_t t, double beta, int ax,
-                                           int ay, int az, Stats& st)
+                                           int ay, int az, int64_t yz, Stats& st)
 {
     if constexpr (B < kGeom[LAT].m) {
         if (B >= b0 && B < b1) {
             LaneState<E> L;
-            trial_read<LAT, E, B, Geo>(A, rep, T, win, tg, r, t, ax, ay, az, L);
+            trial_read<LAT, E, B, Geo>(A, rep, T, win, tg, r, t, ax, ay, az, L, yz);
             tile_finish<LAT, E, Geo>(A, rep, r, t, beta, T, win, L, st);
         }
-        row_trials<LAT, E, Geo, B + 1>(b0, b1, A, rep, T, win, tg, r, t, beta, ax, ay, az, st);
+        row_trials<LAT, E, Geo, B + 1>(b0, b1, A, rep, T, win, tg, r, t, beta, ax, ay, az, yz, st);
     }
 }
 
@@ -1204,6 +1210,7 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
         const bool row_yz = row_in && oy < ey && oz < ez;
         const bool yz = in && row_yz;
         const double beta = ld_const(A.beta, r);
+        const int64_t yz_site = (int64_t)m * rep.L[0] * ((int64_t)(y0 + oy) + (int64_t)rep.L[1] * (z0 + oz));
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (r != r_stats) {
@@ -1215,7 +1222,7 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
         while (true) {
             const int nbb = min(m - b, tau1 - tau);
             if (yz && ox < ex)
-                row_trials<LAT, E, Geo, 0>(b, b + nbb, A, rep, T, win, tg, r, t, beta, x0 + ox, y0 + oy, z0 + oz, st);
+                row_trials<LAT, E, Geo, 0>(b, b + nbb, A, rep, T, win, tg, r, t, beta, x0 + ox, y0 + oy, z0 + oz, yz_site, st);
             tau += nbb;
             if (tau >= tau1) break;
             b = 0;
