@@ -83,6 +83,18 @@ constexpr Geometry make_geometry(int lattice)
 
 constexpr Geometry kGeom[2] = {make_geometry(SMCX_BCC), make_geometry(SMCX_FCC)};
 
+// In lexicographic order the second half of a shell is the first half negated
+// (in reverse), so the first half holds one vector of every +-d pair.
+constexpr bool shells_pair_up(const Geometry& g)
+{
+    for (int s = 0; s < g.nshell; ++s)
+        for (int n = 0; n < g.Z[s]; ++n)
+            for (int a = 0; a < 3; ++a)
+                if (g.v[s][g.Z[s] - 1 - n][a] != -g.v[s][n][a]) return false;
+    return true;
+}
+static_assert(shells_pair_up(kGeom[0]) && shells_pair_up(kGeom[1]), "shells must be sorted lexicographically");
+
 // Neighbour of a basis-b site by half-unit vector (vx, vy, vz): the target
 // basis bt and the displacement (dx, dy, dz) of its conventional cell.
 struct Nb {

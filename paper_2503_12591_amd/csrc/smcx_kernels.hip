@@ -1453,10 +1453,12 @@ __global__ __launch_bounds__(kBlock) void k_pair_counts(const uint8_t* occ, int6
 // Pair counts of up to 4 species through LDS tiles: a block stages TX x TY x
 // 16 conventional cells plus a 2-cell periodic halo of one configuration;
 // lane (x, y) walks the 16 cells along z, forms the packed neighbour
-// histogram of each site per shell (one byte read and one shift-add per
-// neighbour, offsets fixed at compile time) and adds it to 16-bit fields of
-// the row of the site's species.  tiles_per_block keeps every field below
-// 2^16 between flushes.
+// histogram of each site per shell over one direction d of every +-d pair
+// (one byte read and one shift-add per neighbour, offsets fixed at compile
+// time) and adds it to 16-bit fields of the row of the site's species.  These
+// half-shell counts H give the directed counts as C[k][l] = H[k][l] +
+// H[l][k]: the pairs along -d from species k to l are those along +d from l
+// to k.  tiles_per_block keeps every field below 2^16 between flushes.
 // ---------------------------------------------------------------------------
 template <int LAT, int TX>
 __global__ __launch_bounds__(kBlock) void k_pair_counts_tiled(const uint8_t* occ, int64_t N, int L0, int L1, int L2,
@@ -1490,13 +1492,30 @@ __global__ __launch_bounds__(kBlock) void k_pair_counts_tiled(const uint8_t* occ
         const int ty = (int)(tr % nty), tz = (int)(tr / nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
         __syncthreads();  // every lane is done with the previous tile
-        for (int c = threadIdx.x; c < WX * WY * WZ; c += blockDim.x) {
-            const int wx = c % WX, wr = c / WX, wy = wr % WY, wz = wr / WY;
-            const int x = wrap(x0 + wx - kHalo, L0), y = wrap(y0 + wy - kHalo, L1), z = wrap(z0 + wz - kHalo, L2);
-            const int64_t cell = x + (int64_t)L0 * (y + (int64_t)L1 * z);
-            uint8_t* d = win + (wz * WY + wy) * LP + wx * m;
-            if constexpr (m == 2) *(uint16_t*)d = *(const uint16_t*)(o + 2 * cell);
-            else *(uint32_t*)d = *(const uint32_t*)(o + 4 * cell);
+        if constexpr (TX >= 64) {
+            // a wave per window row: its wrapped y, z and base address are
+            // wave-uniform, a lane wraps only its own x
+            const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+            for (int rr = wave; rr < WY * WZ; rr += kBlock / 64) {
+                const int wy = rr % WY, wz = rr / WY;
+                const int y = wrap(y0 + wy - kHalo, L1), z = wrap(z0 + wz - kHalo, L2);
+                const uint8_t* row = o + (int64_t)m * L0 * (y + (int64_t)L1 * z);
+                uint8_t* d = win + (wz * WY + wy) * LP;
+                for (int wx = lane; wx < WX; wx += 64) {
+                    const int x = wrap(x0 + wx - kHalo, L0);
+                    if constexpr (m == 2) *(uint16_t*)(d + 2 * wx) = *(const uint16_t*)(row + 2 * x);
+                    else *(uint32_t*)(d + 4 * wx) = *(const uint32_t*)(row + 4 * x);
+                }
+            }
+        } else {
+            for (int c = threadIdx.x; c < WX * WY * WZ; c += blockDim.x) {
+                const int wx = c % WX, wr = c / WX, wy = wr % WY, wz = wr / WY;
+                const int x = wrap(x0 + wx - kHalo, L0), y = wrap(y0 + wy - kHalo, L1), z = wrap(z0 + wz - kHalo, L2);
+                const int64_t cell = x + (int64_t)L0 * (y + (int64_t)L1 * z);
+                uint8_t* d = win + (wz * WY + wy) * LP + wx * m;
+                if constexpr (m == 2) *(uint16_t*)d = *(const uint16_t*)(o + 2 * cell);
+                else *(uint32_t*)d = *(const uint32_t*)(o + 4 * cell);
+            }
         }
         __syncthreads();
         if (x0 + lx >= L0 || y0 + ly >= L1) continue;
@@ -1508,15 +1527,18 @@ __global__ __launch_bounds__(kBlock) void k_pair_counts_tiled(const uint8_t* occ
 #pragma unroll
                 for (int s = 0; s < kMaxShells; ++s) {
                     if (s < S) {
-                        uint32_t v[kMaxZ];
+                        // one direction of every +-d pair: these half-shell
+                        // counts H give C[k][l] = H[k][l] + H[l][k] exactly
+                        constexpr int kHalfZ = kMaxZ / 2;
+                        uint32_t v[kHalfZ];
 #pragma unroll
-                        for (int n = 0; n < G.Z[s]; ++n) {
+                        for (int n = 0; n < G.Z[s] / 2; ++n) {
                             const Nb nb = nb_of(G, b, G.v[s][n][0], G.v[s][n][1], G.v[s][n][2]);
                             v[n] = win[base + nb.dz * PL + nb.dy * LP + m * nb.dx + (nb.bt - b)];
                         }
                         uint32_t h = 0;
 #pragma unroll
-                        for (int n = 0; n < G.Z[s]; ++n) h += 1u << (8 * v[n]);
+                        for (int n = 0; n < G.Z[s] / 2; ++n) h += 1u << (8 * v[n]);
                         // 8-bit fields (<= 24 each) -> two words of 16-bit fields
                         const uint32_t lo = (h & 0xFFu) | ((h & 0xFF00u) << 8);
                         const uint32_t hi = ((h >> 16) & 0xFFu) | ((h >> 8) & 0xFF0000u);
@@ -1532,20 +1554,30 @@ __global__ __launch_bounds__(kBlock) void k_pair_counts_tiled(const uint8_t* occ
     }
     int64_t* C = counts + (int64_t)blockIdx.y * S * K * K;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int s = 0; s < kMaxShells; ++s) {
+        if (s >= S) continue;
+        // the wave's half-shell counts H[k][l], then C[k][l] and C[l][k] each
+        // gain H[k][l] + H[l][k] in one atomic
+        uint32_t H[4][4];
 #pragma unroll
-        for (int s = 0; s < kMaxShells; ++s)
+        for (int k = 0; k < 4; ++k)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                if (k >= K || s >= S) continue;
-                const uint32_t a = wave_sum(acc[k][s][j] & 0xFFFFu);
-                const uint32_t bsum = wave_sum(acc[k][s][j] >> 16);
-                if ((threadIdx.x & 63) == 0) {
-                    if (2 * j < K && a) atomicAdd((unsigned long long*)&C[(s * K + k) * K + 2 * j], (unsigned long long)a);
-                    if (2 * j + 1 < K && bsum)
-                        atomicAdd((unsigned long long*)&C[(s * K + k) * K + 2 * j + 1], (unsigned long long)bsum);
-                }
+                H[k][2 * j] = k < K ? wave_sum(acc[k][s][j] & 0xFFFFu) : 0u;
+                H[k][2 * j + 1] = k < K ? wave_sum(acc[k][s][j] >> 16) : 0u;
             }
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int l = k; l < 4; ++l) {
+                    const uint32_t c = H[k][l] + H[l][k];
+                    if (l >= K || c == 0) continue;
+                    atomicAdd((unsigned long long*)&C[(s * K + k) * K + l], (unsigned long long)c);
+                    if (l != k) atomicAdd((unsigned long long*)&C[(s * K + l) * K + k], (unsigned long long)c);
+                }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
