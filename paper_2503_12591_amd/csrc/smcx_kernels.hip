@@ -1299,7 +1299,23 @@ __global__ void k_pack(const uint8_t* occ, uint8_t* ws, const RepDev* reps, int 
         z += z < 0 ? L2 : (z >= L2 ? -L2 : 0);
         const uint8_t* src = o + (int64_t)M * L0 * (y + (int64_t)L1 * z);
         uint32_t* dst = (uint32_t*)(pad + (int64_t)row * pitch);
+        // two basis sites, planar rows, a 4-byte aligned natural row: a word
+        // of basis b at x .. x + 3 (no wrap) is bytes b, b + 2, b + 4, b + 6 of
+        // the two aligned natural words at 2 x, and times F byte by byte
+        // (every F * species < 256, so no carry crosses a byte)
+        const bool fast = M == 2 && PLANAR && ((uintptr_t)src & 3) == 0;
+        const int cpw = rep.cp >> 2;
         for (int w = threadIdx.x; w < words; w += blockDim.x) {
+            if (fast) {
+                const int b = w >= cpw ? 1 : 0;
+                const int xw = 4 * (w - b * cpw) - kHalo;
+                if (xw >= 0 && xw + 3 < L0) {
+                    const uint32_t* s32 = (const uint32_t*)(src + 2 * xw);
+                    const uint32_t v = __builtin_amdgcn_perm(s32[1], s32[0], b ? 0x07050301u : 0x06040200u);
+                    dst[w] = v * (uint32_t)F;
+                    continue;
+                }
+            }
             uint32_t v = 0;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -1331,6 +1347,21 @@ __global__ void k_unpack(uint8_t* occ, const uint8_t* ws, const RepDev* reps, in
         const int y = row % L1, z = row / L1;
         const uint8_t* src = pad + ((int64_t)(z + kHalo) * rep.prows + (y + kHalo)) * pitch;
         uint8_t* dst = o + (int64_t)n * row;
+        // two basis sites, planar rows, F = 8, 4-byte aligned rows of a whole
+        // number of words: natural word w (x = 2w, 2w + 1, both basis sites)
+        // interleaves two bytes of each basis column, taken from the aligned
+        // word holding them (x + H is even, so the pair never straddles one)
+        if (M == 2 && PLANAR && F == 8 && (n & 3) == 0 && ((uintptr_t)dst & 3) == 0 && ((uintptr_t)src & 3) == 0) {
+            uint32_t* d32 = (uint32_t*)dst;
+            for (int w = threadIdx.x; w < (n >> 2); w += blockDim.x) {
+                const int c0 = kHalo + 2 * w, c1 = rep.cp + kHalo + 2 * w;  // bytes of (2w, b = 0) and (2w, b = 1)
+                const uint32_t a = *(const uint32_t*)(src + (c0 & ~3)), bb = *(const uint32_t*)(src + (c1 & ~3));
+                const uint32_t o = (uint32_t)(c0 & 3);  // 0 or 2, the same for both columns (cp is a multiple of 16)
+                const uint32_t sel = o | ((4 + o) << 8) | ((o + 1) << 16) | ((5 + o) << 24);
+                d32[w] = (__builtin_amdgcn_perm(bb, a, sel) >> 3) & 0x1F1F1F1Fu;
+            }
+            continue;
+        }
         for (int j = threadIdx.x; j < n; j += blockDim.x) {
             const int x = j / M, b = j - x * M;
             dst[j] = (uint8_t)species_of(src[row_byte<PLANAR>(rep, M, x, b)], F);
