@@ -36,6 +36,33 @@ def test_counts_small_cells_with_duplicate_images(oracle, lattice, dims, K, S):
     assert np.array_equal(C, ref)
 
 
+@pytest.mark.parametrize("lattice,dims,K,S", [(BCC, (2, 2, 2), 2, 2), (BCC, (2, 3, 2), 3, 4),
+                                              (FCC, (2, 2, 3), 3, 4), (BCC, (5, 4, 6), 4, 4), (FCC, (4, 5, 4), 5, 4)])
+def test_half_shell_counts_give_the_directed_counts(oracle, lattice, dims, K, S):
+    """Counting, at every site, one direction d of each +-d pair of a shell
+    (the lexicographically smaller half) gives H with C[k][l] = H[k][l] +
+    H[l][k]: the pairs along -d from species k to l are the pairs along +d
+    from l to k.  This holds also on cells where +d and -d reach the same
+    site (duplicate images)."""
+    N = int(np.prod(dims)) * (2 if lattice == BCC else 4)
+    occ = rand_occ(N, K, 3)
+    dims_a = np.asarray(dims, dtype=np.int64)
+    pos = brute.positions(lattice, dims_a)
+    lookup = {tuple(p): i for i, p in enumerate(pos)}
+    _, vecs = brute.shell_vectors(lattice, S)
+    H = np.zeros((S, K, K), np.int64)
+    for s, vs in enumerate(vecs):
+        vs = sorted(tuple(int(c) for c in v) for v in vs)
+        half, rest = vs[:len(vs) // 2], set(vs[len(vs) // 2:])
+        assert all(tuple(-c for c in v) in rest for v in half)
+        for v in half:
+            q = np.mod(pos + np.asarray(v), 2 * dims_a)
+            j = np.array([lookup[tuple(t)] for t in q])
+            np.add.at(H[s], (occ, occ[j]), 1)
+    C = oracle.pair_counts(lattice, dims, K, S, occ)
+    assert np.array_equal(H + H.transpose(0, 2, 1), C)
+
+
 @pytest.mark.parametrize("lattice,dims,K,S", [(BCC, (6, 5, 4), 4, 4), (FCC, (3, 4, 5), 5, 4)])
 def test_count_invariants(oracle, lattice, dims, K, S):
     N = int(np.prod(dims)) * (2 if lattice == BCC else 4)
