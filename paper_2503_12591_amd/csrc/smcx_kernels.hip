@@ -1282,6 +1282,24 @@ __global__ void k_advance_counter(uint32_t* counter, uint32_t n)
 // (halo rows and columns included: each padded row is the natural row at the
 // wrapped y, z, each byte the site at the wrapped x), a thread one dword of
 // the row at a time; bytes past a column's L0 + 2H sites stay 0.
+// One word of a padded row byte by byte (halo columns wrap to the far side).
+template <int M, bool PLANAR>
+__device__ __forceinline__ uint32_t pack_word(const RepDev& rep, const uint8_t* src, int w, int L0, int F)
+{
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = 4 * w + i;
+        const int b = PLANAR ? j / rep.cp : j % M;
+        int x = (PLANAR ? j - b * rep.cp : j / M) - kHalo;
+        if (b < M && x < L0 + kHalo) {
+            x += x < 0 ? L0 : (x >= L0 ? -L0 : 0);
+            v |= (uint32_t)(src[M * x + b] * F) << (8 * i);
+        }
+    }
+    return v;
+}
+
 template <int M, bool PLANAR>
 __global__ void k_pack(const uint8_t* occ, uint8_t* ws, const RepDev* reps, int r, int F)
 {
@@ -1316,18 +1334,7 @@ __global__ void k_pack(const uint8_t* occ, uint8_t* ws, const RepDev* reps, int 
                     continue;
                 }
             }
-            uint32_t v = 0;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int j = 4 * w + i;
-                const int b = PLANAR ? j / rep.cp : j % M;
-                int x = (PLANAR ? j - b * rep.cp : j / M) - kHalo;
-                if (b < M && x < L0 + kHalo) {
-                    x += x < 0 ? L0 : (x >= L0 ? -L0 : 0);
-                    v |= (uint32_t)(src[M * x + b] * F) << (8 * i);
-                }
-            }
-            dst[w] = v;
+            dst[w] = pack_word<M, PLANAR>(rep, src, w, L0, F);
         }
     }
 }
@@ -1353,12 +1360,27 @@ __global__ void k_unpack(uint8_t* occ, const uint8_t* ws, const RepDev* reps, in
         // word holding them (x + H is even, so the pair never straddles one)
         if (M == 2 && PLANAR && F == 8 && (n & 3) == 0 && ((uintptr_t)dst & 3) == 0 && ((uintptr_t)src & 3) == 0) {
             uint32_t* d32 = (uint32_t*)dst;
-            for (int w = threadIdx.x; w < (n >> 2); w += blockDim.x) {
-                const int c0 = kHalo + 2 * w, c1 = rep.cp + kHalo + 2 * w;  // bytes of (2w, b = 0) and (2w, b = 1)
-                const uint32_t a = *(const uint32_t*)(src + (c0 & ~3)), bb = *(const uint32_t*)(src + (c1 & ~3));
-                const uint32_t o = (uint32_t)(c0 & 3);  // 0 or 2, the same for both columns (cp is a multiple of 16)
-                const uint32_t sel = o | ((4 + o) << 8) | ((o + 1) << 16) | ((5 + o) << 24);
-                d32[w] = (__builtin_amdgcn_perm(bb, a, sel) >> 3) & 0x1F1F1F1Fu;
+            const int nw = n >> 2;
+            // a thread's two words load before either is stored
+            for (int w0 = threadIdx.x; w0 < nw; w0 += 2 * blockDim.x) {
+                uint32_t a[2] = {0u, 0u}, bb[2] = {0u, 0u};
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int w = w0 + u * (int)blockDim.x;
+                    if (w < nw) {
+                        const int c0 = kHalo + 2 * w, c1 = rep.cp + kHalo + 2 * w;  // bytes of (2w, b = 0), (2w, b = 1)
+                        a[u] = *(const uint32_t*)(src + (c0 & ~3));
+                        bb[u] = *(const uint32_t*)(src + (c1 & ~3));
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int w = w0 + u * (int)blockDim.x;
+                    if (w >= nw) continue;
+                    const uint32_t o = (uint32_t)((kHalo + 2 * w) & 3);  // 0 or 2, the same in both columns (cp is a multiple of 16)
+                    const uint32_t sel = o | ((4 + o) << 8) | ((o + 1) << 16) | ((5 + o) << 24);
+                    d32[w] = (__builtin_amdgcn_perm(bb[u], a[u], sel) >> 3) & 0x1F1F1F1Fu;
+                }
             }
             continue;
         }
