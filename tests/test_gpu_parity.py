@@ -132,6 +132,8 @@ def test_trajectories_varied_geometry(smcx, lattice, dims, K, S, ell, tile, mode
     (BCC, (332, 8, 8), 4, 4, 4),      # long padded rows: a wave per window row when staging
     (BCC, (327, 9, 8), 4, 4, 4),      # long rows, uneven cells
     (FCC, (170, 6, 6), 5, 4, 4),      # long FCC rows, 6-bit counters
+    (BCC, (16, 12, 8), 5, 4, 4),      # BCC with 6-bit counters (species codes 6 s)
+    (BCC, (12, 8, 10), 7, 3, 4),      # BCC with 64-bit counters (up to 8 species)
 ])
 def test_stream_rows_and_tiles(smcx, lattice, dims, K, S, ell, rows):
     """Stream mode with whole-row windows (all offsets o_x of a group in one
