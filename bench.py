@@ -641,6 +641,29 @@ def summarize(args):
         with open(os.path.join(ROOT, "profiles", f"traffic_{tag}.json"), "w") as f:
             json.dump({"bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
                        "kernel_build": kernel_fingerprint(), "command": cmd}, f, indent=1)
+    elif kind == "traffic-all":
+        # HBM traffic of every library kernel in the same counter runs, with
+        # its algorithmic bytes where they have a plain definition
+        fd, wd, cfd, cwd, cmd = rest[0], rest[1], rest[2], rest[3], " ".join(rest[4:])
+        ff, _ = _copy_factor(cfd, "FETCH_SIZE")
+        fw, _ = _copy_factor(cwd, "WRITE_SIZE")
+        names = sorted({r["Kernel_Name"] for r in _csv(fd, "counter_collection.csv") if "smcx::" in r["Kernel_Name"]})
+        N = 2 * args.edge ** 3
+        algo = {"k_pair_counts_tiled": (N, 0), "k_pack": (N, None), "k_unpack": (None, N), "k_validate": (N, 0)}
+        lines = [f"# HBM traffic of every library kernel: BCC {args.edge}^3 benchmark, link cell {args.ell}",
+                 f"# command (one pass per counter): {cmd}",
+                 "# FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0 (copy-probe calibration), per dispatch; algorithmic",
+                 "# bytes: the lattice read (pair counts, pack, validate) or written (unpack), N = sites", "",
+                 f"{'kernel':58s} {'read GB':>9s} {'write GB':>9s} {'read / N':>9s}"]
+        for n in names:
+            short = n.split("(")[0].replace("void ", "")
+            rd = _per_dispatch(fd, "FETCH_SIZE", lambda k, n=n: k == n)[0] * 1024 * ff
+            wr = _per_dispatch(wd, "WRITE_SIZE", lambda k, n=n: k == n)[0] * 1024 * fw
+            base = short.split("::")[-1].split("<")[0]
+            ratio = f"{rd / N:9.2f}" if base in algo and algo[base][0] else f"{'':9s}"
+            lines.append(f"{short[:58]:58s} {rd / 1e9:9.3f} {wr / 1e9:9.3f} {ratio}")
+        with open(os.path.join(ROOT, "profiles", f"kernels_{tag}_traffic.txt"), "w") as f:
+            f.write("\n".join(lines) + "\n")
     elif kind == "counters":
         # rest: counter-pass directories, then the command
         dirs = [d for d in rest if os.path.isdir(d)]
