@@ -65,6 +65,7 @@ def lib():
         L.or_philox4x32_10.argtypes = [p, p, p]
         L.or_philox4x32_10.restype = None
         L.or_pair_counts.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p]
+        L.or_pair_counts_threads.argtypes = [C.c_int, p, C.c_int, C.c_int, p, p, i32]
         L.or_energy.argtypes = [C.c_int, C.c_int, p, p]
         L.or_energy.restype = dbl
         L.or_sro.argtypes = [C.c_int, C.c_int, p, p, p]
@@ -132,10 +133,15 @@ def philox(ctr, key) -> np.ndarray:
     return out
 
 
-def pair_counts(lattice: int, dims, K: int, S: int, occ: np.ndarray) -> np.ndarray:
+def pair_counts(lattice: int, dims, K: int, S: int, occ: np.ndarray, nthreads: int = 1) -> np.ndarray:
+    """Directed pair counts C[S][K][K]; nthreads > 1 splits the sites over
+    OpenMP threads (same integer result)."""
     occ = np.ascontiguousarray(occ, dtype=np.uint8)
     Cn = np.zeros((S, K, K), np.int64)
-    rc = lib().or_pair_counts(lattice, _ptr(_dims(dims)), K, S, _ptr(occ), _ptr(Cn))
+    if nthreads > 1:
+        rc = lib().or_pair_counts_threads(lattice, _ptr(_dims(dims)), K, S, _ptr(occ), _ptr(Cn), nthreads)
+    else:
+        rc = lib().or_pair_counts(lattice, _ptr(_dims(dims)), K, S, _ptr(occ), _ptr(Cn))
     if rc != 0:
         raise ValueError("or_pair_counts failed")
     return Cn

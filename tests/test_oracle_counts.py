@@ -26,6 +26,17 @@ def test_counts_vs_min_image_pairs(oracle, lattice, dims, K, S):
     assert np.array_equal(C, ref)
 
 
+@pytest.mark.parametrize("nthreads", [2, 3, 7])
+def test_threaded_counts_vs_min_image_pairs(oracle, nthreads):
+    """The threaded counts (sites split over threads, tables added) against
+    brute force, with site ranges that do not divide evenly."""
+    for lattice, dims, K, S in [(BCC, (5, 4, 6), 4, 4), (FCC, (4, 5, 4), 5, 3)]:
+        N = int(np.prod(dims)) * (2 if lattice == BCC else 4)
+        occ = rand_occ(N, K, 3)
+        C = oracle.pair_counts(lattice, dims, K, S, occ, nthreads=nthreads)
+        assert np.array_equal(C, brute.counts_min_image(lattice, dims, S, occ, K))
+
+
 @pytest.mark.parametrize("lattice,dims,K,S", [(BCC, (2, 2, 2), 2, 2), (BCC, (2, 3, 2), 3, 4),
                                               (FCC, (2, 2, 3), 3, 4), (BCC, (3, 3, 3), 4, 4)])
 def test_counts_small_cells_with_duplicate_images(oracle, lattice, dims, K, S):

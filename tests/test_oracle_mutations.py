@@ -64,6 +64,24 @@ MUTANTS = [
      ["test_oracle_qsro.py::test_delta_e_is_the_total_energy_difference"]),
     ("qSRO affected set with duplicates", "dup = v[j][0] == cand[i][0] && v[j][1] == cand[i][1] && v[j][2] == cand[i][2];",
      "dup = 0;", ["test_oracle_qsro.py::test_delta_e_is_the_total_energy_difference"]),
+    ("replay keyed on the site only",
+     "if (rp->replay[i].replica == r && rp->replay[i].sweep == t && rp->replay[i].site == a) {",
+     "if (rp->replay[i].site == a) {",
+     ["test_oracle_ties.py::test_replay_under_other_keys_is_ignored",
+      "test_oracle_ties.py::test_replay_keyed_by_replica_and_sweep"]),
+    ("replay keyed without the sweep",
+     "if (rp->replay[i].replica == r && rp->replay[i].sweep == t && rp->replay[i].site == a) {",
+     "if (rp->replay[i].replica == r && rp->replay[i].site == a) {",
+     ["test_oracle_ties.py::test_replay_keyed_by_replica_and_sweep"]),
+    ("replayed decision ignored", "if (rp && replay_lookup(rp, (int32_t)r, t, a, &dec)) accept = dec;",
+     "if (rp && replay_lookup(rp, (int32_t)r, t, a, &dec)) accept = accept;",
+     ["test_oracle_ties.py::test_replay_flips_exactly_the_tied_swap"]),
+    ("trial near-tie never detected", "accept = u < P;\n            if (fabs(u - P) < 1e-12) {\n                flags |= TR_TIE;",
+     "accept = u < P;\n            if (fabs(u - P) < 0.0) {\n                flags |= TR_TIE;",
+     ["test_oracle_ties.py::test_forced_trial_tie_is_logged"]),
+    ("exchange replay keyed on the replica", "if (replay_lookup(&rp, -1, round, i, &dec)) accept = dec;",
+     "if (replay_lookup(&rp, -1, round, a, &dec)) accept = dec;",
+     ["test_oracle_ties.py::test_exchange_replay_flips_the_tied_pair"]),
 ]
 
 
