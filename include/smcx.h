@@ -141,11 +141,22 @@ int smcx_min_cell_edge(int32_t lattice, int32_t n_shells);
  * working copy of the occupancy with a 2-cell periodic halo. */
 int smcx_workspace_size(const smcx_desc *desc, size_t *bytes);
 
-/* Create a handle.  occ_dev: device uint8 [sum_r N_r], replicas back to back
- * in site-index order; ws_dev: device workspace of ws_bytes >=
- * smcx_workspace_size, 256-byte aligned.  Uploads the tables on `stream`,
- * checks on the device that every species is < K, and synchronises.
- * The handle keeps both pointers; their memory must outlive it. */
+/* Create a handle for R replicas of one lattice kind: the configuration
+ * (one species per site), the coordination shells of the energy model and
+ * the partition of each replica into link cells whose trials of one
+ * mini-step are independent (Methods, "Implementation of SMC-GPU", link-cell
+ * bullet; Fig. 7; Results, "Performance of the SMC-X algorithm", the
+ * LIZ / LIZ+ argument).
+ *   occ_dev  device uint8 [sum_r N_r], replicas back to back in site-index
+ *            order; every value must be < K.  Caller-owned; the sweeps
+ *            mutate it in place.
+ *   ws_dev   device workspace of ws_bytes >= smcx_workspace_size, 256-byte
+ *            aligned, caller-owned.
+ * Uploads the tables on `stream`, checks on the device that every species
+ * is < K, and synchronises.  The handle keeps both pointers; their memory
+ * must outlive it.  Errors: SMCX_E_INVALID_ARG (bad description, a species
+ * >= K, a partition below the minimum edge, misaligned or NULL pointers),
+ * SMCX_E_WORKSPACE (ws_bytes too small), SMCX_E_HIP. */
 int smcx_lattice_init(smcx_lattice **out, const smcx_desc *desc, uint8_t *occ_dev, void *ws_dev,
                       size_t ws_bytes, void *stream);
 
@@ -153,19 +164,33 @@ int smcx_lattice_destroy(smcx_lattice *h);
 
 /* Partition actually used by replica r: ncell_out[3] cells per axis and the
  * edges (x cells, then y, then z) in cells_out, which must hold
- * Lx + Ly + Lz entries; *n_ministeps = M_x*M_y*M_z*m.  Feed these to a replay
- * of the same trajectory. */
+ * Lx + Ly + Lz entries (host memory, caller-owned); *n_ministeps =
+ * M_x*M_y*M_z*m, the n_A sequential mini-steps of a sweep (Fig. 7 caption:
+ * the outer loop over the site index within a link cell is sequential, the
+ * inner loop over link cells parallel; Tab. 4 for link cells of 3 and 4).
+ * Feed these to a replay of the same trajectory.  Errors:
+ * SMCX_E_INVALID_ARG (NULL pointers, replica out of range). */
 int smcx_get_schedule(const smcx_lattice *h, int32_t replica, int32_t *ncell_out,
                       int32_t *cells_out, int32_t *n_ministeps);
 
-/* Set the EPI tensor V (host, binary64, [S][K][K], eV).  V must be symmetric
- * in (k, l) exactly.  Tables D[s][t][p][q] = V_s[q][t] - V_s[p][t] are uploaded
- * on `stream`, which is synchronised. */
+/* Set the EPI tensor V (host, binary64, [S][K][K], eV; copied): the pair
+ * interaction of species k and l at shell distance s (Methods, "The EPI and
+ * qSRO model", Eq. Linear_EPI and Eq. Total_EPI, with the energy written as
+ * E = 1/2 sum_i sum_s sum_{d in D_s} V_s[sigma_i][sigma_{i+d}]).  V must be
+ * symmetric in (k, l) exactly.  Tables D[s][t][p][q] = V_s[q][t] - V_s[p][t]
+ * are uploaded on `stream`, which is synchronised.  Errors:
+ * SMCX_E_INVALID_ARG (NULL, asymmetric or non-finite V), SMCX_E_HIP. */
 int smcx_set_epi(smcx_lattice *h, const double *V, void *stream);
 
 /*
  * Run n_sweeps sweeps on every replica, global sweep indices first_sweep ..
- * first_sweep + n_sweeps - 1, mutating occ_dev in place.
+ * first_sweep + n_sweeps - 1, mutating occ_dev in place.  A sweep is the n_A
+ * mini-steps in order, a mini-step one swap trial in every link cell
+ * (Methods, "Implementation of SMC-GPU", link-cell and random-number
+ * bullets; Fig. 7); a trial swaps a site with a random nearest neighbour and
+ * is accepted with probability min(1, exp(-beta dE)) (Supplementary, "Monte
+ * Carlo Simulation Algorithms", the acceptance equation), dE being twice
+ * the change of the two local energies (Methods, "The EPI and qSRO model").
  *   beta_dev   device double [n_sweeps][R] inverse temperatures (1/eV)
  *   stats_dev  device int64 [R][3], incremented by attempted, accepted and
  *              near-tie counts
@@ -173,7 +198,9 @@ int smcx_set_epi(smcx_lattice *h, const double *V, void *stream);
  *   tie_count_dev device int32 [1]: incremented once per near-tie; entries
  *              past tie_cap are counted but not stored
  *   mode       SMCX_MODE_*
- * Asynchronous on `stream`.
+ * All pointers are device memory owned by the caller.  Asynchronous on
+ * `stream`.  Errors: SMCX_E_INVALID_ARG (negative n_sweeps, missing buffers,
+ * bad mode), SMCX_E_NOT_READY before smcx_set_epi, SMCX_E_HIP.
  */
 int smcx_sweep(smcx_lattice *h, int32_t n_sweeps, uint64_t seed, uint32_t first_sweep,
                const double *beta_dev, int64_t *stats_dev, smcx_tie *ties_dev, int32_t tie_cap,
@@ -204,9 +231,12 @@ int smcx_pair_counts(smcx_lattice *h, int64_t *counts_dev, void *stream);
 int smcx_energy(smcx_lattice *h, int64_t *counts_dev, double *E_host, void *stream);
 
 /* Warren-Cowley short-range order alpha[r][s][k][l] =
- * 1 - C N / (Z_s N_k N_l) into alpha_host [R][S][K][K] (host double).
- * Returns SMCX_E_INVALID_ARG when a species is absent from a replica.
- * Synchronises the stream. */
+ * 1 - C N / (Z_s N_k N_l) into alpha_host [R][S][K][K] (host double,
+ * caller-owned), from the directed pair counts (recomputed into counts_dev
+ * as for smcx_pair_counts).  The textbook parameter (Cowley 1950) over the
+ * per-shell pair numbers that the paper's pair fractions pi_m^{pp'} are built
+ * from (Methods, "The EPI and qSRO model").  Returns SMCX_E_INVALID_ARG when
+ * a species is absent from a replica.  Synchronises the stream. */
 int smcx_sro(smcx_lattice *h, int64_t *counts_dev, double *alpha_host, void *stream);
 
 /* Energies as smcx_energy, left on the device: counts_dev [R][S][K][K] int64
@@ -247,23 +277,6 @@ int smcx_exchange(smcx_lattice *h, int32_t round, uint64_t seed, const double *b
                   double *E_dev, int64_t *xstats_dev, smcx_tie *ties_dev, int32_t tie_cap,
                   int32_t *tie_count_dev, void *stream);
 
-/* Stepwise anneal with energy recording (the paper's protocol: start hot,
- * lower T in steps, discard sweeps at each temperature before measuring;
- * Methods, MC simulation paragraph after Tab. 4).  Step s = 0 .. n_steps-1
- * runs `warmup` sweeps, then `record` sweeps each followed by the energies
- * of every replica, all at beta_steps_dev[s][r]; sweep indices run from
- * first_sweep on, (warmup + record) per step.
- *   beta_steps_dev [n_steps][R] binary64 (device).
- *   counts_dev [R][S][K][K] int64: scratch, overwritten.
- *   E_dev [n_steps][record][R] binary64: recorded energies (smcx_energy_dev).
- *   cv_dev [n_steps][R] binary64: heat capacity per site in units of k_B,
- *     beta^2 Var(E) / N_r over the step's recorded energies (two passes,
- *     j ascending: m = sum E / n, v = sum (E - m)^2 / n, c = beta beta v / N).
- *   stats_dev, ties_dev, tie_cap, tie_count_dev, mode: as for smcx_sweep.
- * counts_dev, E_dev and cv_dev may be NULL when record == 0.  Everything is
- * enqueued on `stream` without host synchronisation.  Errors:
- * SMCX_E_INVALID_ARG (negative sizes, missing buffers, sweep index past
- * 2^32), SMCX_E_NOT_READY before smcx_set_epi. */
 /* qSRO model (Methods, "The EPI and qSRO model", Eq. quadratic_local_SRO):
  * the local energy of a site with species p is
  *   E_i = sum_m sum_t V_m[p][t] (n_i[m][t] / Z_m) + sum_m W_m[p] (n_i[m][p] / Z_m)^2
@@ -319,28 +332,82 @@ int smcx_local_energy(smcx_lattice *h, int32_t replica, double *e_dev, void *str
 int smcx_clusters(smcx_lattice *h, int32_t replica, const double *e_dev, double threshold,
                   int32_t *label_dev, int32_t *size_dev, int64_t *n_clusters_dev, void *stream);
 
+/* Stepwise anneal with energy recording (the paper's protocol: start hot,
+ * lower T in steps, discard sweeps at each temperature before measuring;
+ * Methods, MC simulation paragraph after Tab. 4).  Step s = 0 .. n_steps-1
+ * runs `warmup` sweeps, then `record` sweeps each followed by the energies
+ * of every replica, all at beta_steps_dev[s][r]; sweep indices run from
+ * first_sweep on, (warmup + record) per step.
+ *   beta_steps_dev [n_steps][R] binary64 (device).
+ *   counts_dev [R][S][K][K] int64: scratch, overwritten.
+ *   E_dev [n_steps][record][R] binary64: recorded energies (smcx_energy_dev).
+ *   cv_dev [n_steps][R] binary64: heat capacity per site in units of k_B,
+ *     beta^2 Var(E) / N_r over the step's recorded energies (two passes,
+ *     j ascending: m = sum E / n, v = sum (E - m)^2 / n, c = beta beta v / N).
+ *   stats_dev, ties_dev, tie_cap, tie_count_dev, mode: as for smcx_sweep.
+ * counts_dev, E_dev and cv_dev may be NULL when record == 0.  Everything is
+ * enqueued on `stream` without host synchronisation.  Errors:
+ * SMCX_E_INVALID_ARG (negative sizes, missing buffers, sweep index past
+ * 2^32), SMCX_E_NOT_READY before smcx_set_epi. */
 int smcx_anneal(smcx_lattice *h, int32_t n_steps, int32_t warmup, int32_t record, uint64_t seed,
                 uint32_t first_sweep, const double *beta_steps_dev, int64_t *counts_dev, double *E_dev,
                 double *cv_dev, int64_t *stats_dev, smcx_tie *ties_dev, int32_t tie_cap,
                 int32_t *tie_count_dev, int32_t mode, void *stream);
 
-/* Stateless batched pair counts for B configurations of one geometry:
- * occ_batch_dev device uint8 [B][N] (N = m * dims[0]*dims[1]*dims[2]),
- * counts_dev device int64 [B][S][K][K] (overwritten).  The gradient of
- * E_b = 1/2 <C_b, V> with respect to V is C_b / 2.  Asynchronous. */
+/* Backward of the energy with respect to the EPI: stateless batched pair
+ * counts for B configurations of one geometry.  E_b = 1/2 <C_b, V> is linear
+ * in V, so dE_b/dV = C_b / 2; the paper fits its EPI by Adam and
+ * back-propagation on these features (Methods, "The EPI and qSRO model",
+ * Eq. Total_EPI and the fitting paragraph).
+ *   dims          host int32 [3], conventional cells per axis (each >= 2)
+ *   occ_batch_dev device uint8 [B][N] (N = m * dims[0]*dims[1]*dims[2]),
+ *                 every value < n_species (checked on the device)
+ *   counts_dev    device int64 [B][S][K][K] (overwritten)
+ * Device memory owned by the caller.  Asynchronous, except that a species
+ * check failure is reported: the call synchronises `stream` to read the
+ * check's flag.  Errors: SMCX_E_INVALID_ARG (bad lattice, K, S, dims, B,
+ * NULL pointers, a lattice so small that a site is its own neighbour, a
+ * species >= n_species), SMCX_E_HIP. */
 int smcx_energy_backward(int32_t lattice, const int32_t *dims, int32_t n_species,
                          int32_t n_shells, const uint8_t *occ_batch_dev, int32_t B,
                          int64_t *counts_dev, void *stream);
 
+/* Energies of B configurations from their pair counts (the forward of the
+ * EPI fit; Methods, "The EPI and qSRO model", Eq. Total_EPI: the energy is
+ * linear in the pair numbers):
+ *   E_dev[b] = 1/2 sum_i counts_dev[b][i] V_dev[i], i ascending, binary64
+ * (the rounding of smcx_energy), with n_terms = S*K*K entries per
+ * configuration.  counts_dev device int64 [B][n_terms] (from
+ * smcx_energy_backward), V_dev device double [n_terms], E_dev device double
+ * [B]; caller-owned.  Asynchronous.  Errors: SMCX_E_INVALID_ARG (B < 0,
+ * n_terms < 1, NULL pointers), SMCX_E_HIP. */
+int smcx_energy_of_counts(const int64_t *counts_dev, const double *V_dev, int32_t B, int32_t n_terms,
+                          double *E_dev, void *stream);
+
+/* Gradient of sum_b g[b] E_b with respect to V for E_b = 1/2 <C_b, V> (the
+ * back-propagation step of the EPI fit; Methods, "The EPI and qSRO model"):
+ *   grad_dev[i] = 1/2 sum_b g_dev[b] counts_dev[b][i], b ascending, binary64.
+ * counts_dev device int64 [B][n_terms], g_dev device double [B], grad_dev
+ * device double [n_terms] (overwritten; zero when B == 0); caller-owned.
+ * Asynchronous.  Errors: SMCX_E_INVALID_ARG, SMCX_E_HIP. */
+int smcx_energy_grad(const int64_t *counts_dev, const double *g_dev, int32_t B, int32_t n_terms, double *grad_dev,
+                     void *stream);
+
 /*
- * Temperature ladder as a replayable graph.  Captures, on `stream`, one
+ * Temperature ladder as a replayable graph (temperatures are independent
+ * chains, the paper's temperature parallelism: Supplementary, "Parallelization
+ * opportunities in Monte Carlo simulation"; Methods after Tab. 4, the two GPUs
+ * used by temperature parallelization).  Captures, on `stream`, one
  * persistent launch that runs n_sweeps sweeps on every replica with the
  * fixed inverse temperatures beta_dev [R] (device double).  The first sweep
  * index is read from *sweep_counter_dev (device uint32) when the graph runs
  * and advanced by n_sweeps at its end, so every replay continues the chain.
  * *graph_out receives an executable graph for smcx_graph_launch.  `stream`
  * must be a created stream (the legacy default stream cannot be captured);
- * nothing runs during the capture.
+ * nothing runs during the capture.  All pointers are device memory owned by
+ * the caller and must outlive the graph; the graph is destroyed with
+ * smcx_graph_destroy.  Errors: SMCX_E_INVALID_ARG, SMCX_E_NOT_READY before
+ * smcx_set_epi, SMCX_E_HIP (capture failed).
  */
 int smcx_ladder_capture(smcx_lattice *h, int32_t n_sweeps, uint64_t seed, const double *beta_dev,
                         uint32_t *sweep_counter_dev, int64_t *stats_dev, smcx_tie *ties_dev,

@@ -1253,12 +1253,45 @@ int smcx_energy_backward(int32_t lattice, const int32_t* dims, int32_t n_species
     const int64_t N = (int64_t)lattice_m(lattice) * dims[0] * dims[1] * dims[2];
     hipStream_t st = (hipStream_t)stream;
     const int64_t per = (int64_t)n_shells * n_species * n_species;
+    // species check: the flag lives in the first word of counts_dev, which
+    // the counts overwrite afterwards (a species >= K would shift a counter
+    // field out of range and silently miscount)
+    {
+        int32_t* bad = (int32_t*)counts_dev;
+        SMCX_HIP(launch_fill_i32(bad, 1, 0, st));
+        SMCX_HIP(launch_validate(occ_batch_dev, N * (int64_t)B, n_species, bad, st));
+        int32_t bad_h = 0;
+        SMCX_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        SMCX_HIP(hipStreamSynchronize(st));
+        if (bad_h) return fail(SMCX_E_INVALID_ARG, "a configuration holds a species >= n_species");
+    }
     SMCX_HIP(launch_fill_i64(counts_dev, per * B, 0, st));
     for (int32_t b0 = 0; b0 < B; b0 += 65535) {
         const int nb = std::min<int32_t>(65535, B - b0);
         SMCX_HIP(launch_pair_counts(lattice, n_species, n_shells, occ_batch_dev + (int64_t)b0 * N, N, dims, nb,
                                     counts_dev + per * b0, st));
     }
+    return SMCX_OK;
+}
+
+int smcx_energy_of_counts(const int64_t* counts_dev, const double* V_dev, int32_t B, int32_t n_terms,
+                          double* E_dev, void* stream)
+{
+    if (B < 0 || n_terms < 1) return fail(SMCX_E_INVALID_ARG, "B must be >= 0 and n_terms >= 1");
+    if (B == 0) return SMCX_OK;
+    if (!counts_dev || !V_dev || !E_dev) return fail(SMCX_E_INVALID_ARG, "NULL device pointer");
+    SMCX_HIP(launch_energy(counts_dev, V_dev, B, n_terms, E_dev, (hipStream_t)stream));
+    return SMCX_OK;
+}
+
+int smcx_energy_grad(const int64_t* counts_dev, const double* g_dev, int32_t B, int32_t n_terms, double* grad_dev,
+                     void* stream)
+{
+    if (B < 0 || n_terms < 1) return fail(SMCX_E_INVALID_ARG, "B must be >= 0 and n_terms >= 1");
+    if (!counts_dev && B > 0) return fail(SMCX_E_INVALID_ARG, "NULL device pointer");
+    if (!g_dev && B > 0) return fail(SMCX_E_INVALID_ARG, "NULL device pointer");
+    if (!grad_dev) return fail(SMCX_E_INVALID_ARG, "NULL device pointer");
+    SMCX_HIP(launch_energy_grad(counts_dev, g_dev, B, n_terms, grad_dev, (hipStream_t)stream));
     return SMCX_OK;
 }
 

@@ -2349,6 +2349,25 @@ hipError_t launch_energy(const int64_t* C, const double* V, int R, int SKK, doub
     return hipGetLastError();
 }
 
+// Gradient of sum_b g_b E_b with respect to V for E_b = 1/2 <C_b, V>:
+// grad[i] = 1/2 sum_b g_b C_b[i], b ascending in binary64, one thread per
+// entry i of V.
+__global__ void k_energy_grad(const int64_t* C, const double* g, int B, int SKK, double* grad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= SKK) return;
+    double acc = 0.0;
+    for (int b = 0; b < B; ++b) acc = acc + g[b] * (double)C[(int64_t)b * SKK + i];
+    grad[i] = 0.5 * acc;
+}
+
+hipError_t launch_energy_grad(const int64_t* C, const double* g, int B, int SKK, double* grad, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_energy_grad, dim3((unsigned)((SKK + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, C, g, B,
+                       SKK, grad);
+    return hipGetLastError();
+}
+
 hipError_t launch_exchange(const double* E, const double* beta_slot, int32_t* rep_at, int R, uint64_t seed,
                            uint32_t round, double* beta_rows, int n_rows, int64_t* xstats, smcx_tie* ties,
                            int32_t tie_cap, int32_t* tie_count, hipStream_t st)

@@ -30,7 +30,7 @@ EXPORTS = [
     "smcx_sweep_capture",
     "smcx_graph_launch", "smcx_graph_destroy", "smcx_timing_enable", "smcx_timing_read",
     "smcx_energy_dev", "smcx_exchange", "smcx_anneal", "smcx_local_energy", "smcx_clusters",
-    "smcx_set_qsro", "smcx_sweep_qsro",
+    "smcx_set_qsro", "smcx_sweep_qsro", "smcx_energy_of_counts", "smcx_energy_grad",
 ]
 
 
@@ -72,6 +72,8 @@ def lib():
     L.smcx_energy.argtypes = [p, p, p, p]
     L.smcx_sro.argtypes = [p, p, p, p]
     L.smcx_energy_backward.argtypes = [i32, p, i32, i32, p, i32, p, p]
+    L.smcx_energy_of_counts.argtypes = [p, p, i32, i32, p, p]
+    L.smcx_energy_grad.argtypes = [p, p, i32, i32, p, p]
     L.smcx_ladder_capture.argtypes = [p, i32, u64, p, p, p, p, i32, p, p, C.POINTER(p)]
     L.smcx_sweep_capture.argtypes = [p, i32, u64, p, p, p, p, i32, p, i32, p, C.POINTER(p)]
     L.smcx_graph_launch.argtypes = [p, p]
@@ -480,26 +482,53 @@ def energy_backward_counts(lattice: int, dims, K: int, S: int, occ_batch):
     return counts
 
 
+def energy_of_counts(counts, V):
+    """E_b = 1/2 <C_b, V> (CUDA float64 [B]) from int64 counts [B][S][K][K]
+    and a float64 V [S][K][K] (smcx_energy_of_counts)."""
+    torch = _torch()
+    counts = counts.contiguous()
+    V = V.detach().to(dtype=torch.float64).contiguous()
+    B = counts.shape[0]
+    E = torch.empty(B, dtype=torch.float64, device="cuda")
+    _check(lib().smcx_energy_of_counts(_ptr(counts), _ptr(V), B, V.numel(), _ptr(E), _stream(torch)))
+    return E
+
+
+def energy_grad(counts, g):
+    """1/2 sum_b g_b C_b (CUDA float64 [S][K][K]) (smcx_energy_grad)."""
+    torch = _torch()
+    counts = counts.contiguous()
+    g = g.detach().to(dtype=torch.float64).contiguous()
+    B = counts.shape[0]
+    grad = torch.empty(counts.shape[1:], dtype=torch.float64, device="cuda")
+    _check(lib().smcx_energy_grad(_ptr(counts), _ptr(g), B, grad.numel(), _ptr(grad), _stream(torch)))
+    return grad
+
+
 def _make_energy_fn():
     import torch
 
     class EnergyFn(torch.autograd.Function):
         """E_b = 1/2 <C_b, V> for a batch of configurations; dE_b/dV = C_b / 2.
 
-        The counts come from the HIP pair-count kernel; the forward product and
-        the backward scaling are the only torch arithmetic."""
+        The counts come from the HIP pair-count kernel (smcx_energy_backward),
+        the energies and the gradient from smcx_energy_of_counts and
+        smcx_energy_grad, all in binary64.  `counts` may pass the batch's
+        counts when they are already known (they do not depend on V)."""
 
         @staticmethod
-        def forward(ctx, V, occ_batch, lattice, dims):
+        def forward(ctx, V, occ_batch, lattice, dims, counts=None):
             S, K, _ = V.shape
-            counts = energy_backward_counts(lattice, dims, K, S, occ_batch).to(V.dtype)
+            if counts is None:
+                counts = energy_backward_counts(lattice, dims, K, S, occ_batch)
             ctx.save_for_backward(counts)
-            return 0.5 * (counts * V.unsqueeze(0)).sum(dim=(1, 2, 3))
+            ctx.v_dtype = V.dtype
+            return energy_of_counts(counts, V).to(V.dtype)
 
         @staticmethod
         def backward(ctx, g):
             (counts,) = ctx.saved_tensors
-            return 0.5 * (g.view(-1, 1, 1, 1) * counts).sum(dim=0), None, None, None
+            return energy_grad(counts, g).to(ctx.v_dtype), None, None, None, None
 
     return EnergyFn
 
@@ -614,7 +643,9 @@ def fit_epi(lattice: int, dims, K: int, S: int, occ_batch, e_per_site, steps: in
                         else e_per_site, dtype=torch.float64).cuda().reshape(-1)
     ku, lu = np.triu_indices(K, 1)
     ku_t, lu_t = torch.tensor(ku).cuda(), torch.tensor(lu).cuda()
-    counts = energy_backward_counts(lattice, dims, K, S, occ_batch).to(torch.float64)
+    # the counts do not depend on V: one batched count serves every Adam step
+    counts_i = energy_backward_counts(lattice, dims, K, S, occ_batch)
+    counts = counts_i.to(torch.float64)
     F = counts[:, :, ku_t, lu_t].reshape(B, -1) / N
     Fc = F - F.mean(dim=0)
     L = torch.linalg.cholesky(Fc.T @ Fc / B)
@@ -636,7 +667,7 @@ def fit_epi(lattice: int, dims, K: int, S: int, occ_batch, e_per_site, steps: in
     loss = None
     for _ in range(steps):
         opt.zero_grad()
-        e = fn.apply(v_of(theta), occ_batch, lattice, dims) / N
+        e = fn.apply(v_of(theta), occ_batch, lattice, dims, counts_i) / N
         r = (e - e.mean()) - yc
         loss = (r * r).mean() / scale
         loss.backward()

@@ -80,7 +80,50 @@ def test_energy_backward_batch_and_autograd(smcx):
     expect = 0.5 * (np.arange(1, B + 1)[:, None, None, None] * C).sum(axis=0)
     assert np.allclose(V.grad.cpu().numpy(), expect, rtol=0, atol=1e-9)
     Eref = [O.energy(C[b], V.detach().cpu().numpy()) for b in range(B)]
-    assert np.allclose(E.detach().cpu().numpy(), Eref, rtol=1e-12, atol=0)
+    # the same binary64 sum as the oracle's (s, k, l ascending)
+    assert np.array_equal(E.detach().cpu().numpy(), np.array(Eref))
+
+
+def test_energy_autograd_gradcheck_and_central_differences(smcx):
+    """The HIP autograd path of E(sigma; V) against finite differences of its
+    own forward: torch.autograd.gradcheck in binary64 on a small batch, and
+    central differences of the summed energy along every entry of V (E is
+    linear in V, so the differences are exact up to rounding)."""
+    import torch
+    dims, K, S, B = (4, 4, 4), 3, 4, 5
+    occs = np.stack([rand_occ(128, K, 200 + b, equi=False) for b in range(B)])
+    t = torch.from_numpy(occs).cuda()
+    fn = smcx.EnergyFn()
+    V = torch.tensor(sym_V(S, K, 0.05, 9), dtype=torch.float64, device="cuda", requires_grad=True)
+    say("gradcheck EnergyFn")
+    assert torch.autograd.gradcheck(lambda v: fn.apply(v, t, BCC, dims), (V,), eps=1e-6, atol=1e-8, rtol=1e-7)
+    g = torch.tensor(np.random.default_rng(3).normal(size=B), dtype=torch.float64, device="cuda")
+    (fn.apply(V, t, BCC, dims) * g).sum().backward()
+    grad = V.grad.cpu().numpy()
+    h = 1e-3
+    Vn = V.detach()
+    fd = np.zeros_like(grad)
+    for idx in np.ndindex(S, K, K):
+        e = torch.zeros_like(Vn)
+        e[idx] = h
+        plus = float((fn.apply(Vn + e, t, BCC, dims) * g).sum())
+        minus = float((fn.apply(Vn - e, t, BCC, dims) * g).sum())
+        fd[idx] = (plus - minus) / (2 * h)
+    assert np.allclose(grad, fd, rtol=1e-9, atol=1e-9), np.abs(grad - fd).max()
+    # and against brute-force counts: d/dV of sum_b g_b E_b is 1/2 sum_b g_b C_b
+    Cref = np.stack([O.pair_counts(BCC, dims, K, S, occs[b]) for b in range(B)])
+    expect = 0.5 * np.einsum("b,bskl->skl", g.cpu().numpy(), Cref)
+    assert np.allclose(grad, expect, rtol=1e-13, atol=1e-12)
+
+
+def test_energy_backward_rejects_bad_species(smcx):
+    import torch
+    occ = rand_occ(2 * 64, 4, 5)
+    occ[77] = 4  # species 4 with K = 4
+    t = torch.from_numpy(np.stack([rand_occ(128, 4, 6), occ])).cuda()
+    with pytest.raises(smcx.SmcxError):
+        smcx.energy_backward_counts(BCC, (4, 4, 4), 4, 2, t)
+    torch.cuda.synchronize()
 
 
 @pytest.mark.parametrize("mode", ["persistent", "stream", "plain"])

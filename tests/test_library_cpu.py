@@ -129,6 +129,16 @@ def test_stateless_backward_rejects_bad_args(smcx):
     assert rc == 0
 
 
+def test_energy_of_counts_and_grad_reject_bad_args(smcx):
+    L = smcx.lib()
+    assert L.smcx_energy_of_counts(None, None, -1, 64, None, None) == -1
+    assert L.smcx_energy_of_counts(None, None, 3, 0, None, None) == -1
+    assert L.smcx_energy_of_counts(None, None, 3, 64, None, None) == -1
+    assert L.smcx_energy_of_counts(None, None, 0, 64, None, None) == 0  # empty batch: no-op
+    assert L.smcx_energy_grad(None, None, 2, 64, None, None) == -1
+    assert L.smcx_energy_grad(None, None, -1, 64, None, None) == -1
+
+
 def test_null_handle_calls_fail_cleanly(smcx):
     L = smcx.lib()
     assert L.smcx_set_epi(None, None, None) == -1
