@@ -82,11 +82,34 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": n, "launches": 3}))
 
 
+def host_cpu():
+    """CPU model (first "model name" of /proc/cpuinfo), the CPUs the machine
+    reports and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, allowed
+
+
 def cpu_baseline(lattice, dims, K, S, cells, occ_host, V, seed, beta, budget_s):
     """The oracle on a bounded sample of the same workload: the first mini-steps
-    of sweep 0 on the same lattice, all host threads (at most 16)."""
+    of sweep 0 on the same lattice, on the threads the host grants this job
+    (OMP_NUM_THREADS, else every CPU the process may use), and the next
+    mini-step on one thread."""
     from oracle import oracle as O
-    nthreads = max(1, min(16, O.max_threads()))
+    model, ncpu, allowed = host_cpu()
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    nthreads = int(env) if env.isdigit() and int(env) > 0 else allowed
     occ = occ_host.copy()
     t0 = time.perf_counter()
     r = O.run_ministeps(lattice, dims, K, S, cells, occ, V, seed, beta, 0, 0, 1, nthreads=nthreads)
@@ -94,16 +117,24 @@ def cpu_baseline(lattice, dims, K, S, cells, occ_host, V, seed, beta, budget_s):
     trials = int(r.stats[0])
     n_more = max(0, int(budget_s / max(t1, 1e-3)) - 1)
     nA = int(np.prod([max(c) for c in cells])) * (2 if lattice == 0 else 4)
-    n_more = min(n_more, nA - 1)
+    n_more = min(n_more, nA - 2)
     if n_more > 0:
         t0 = time.perf_counter()
         r2 = O.run_ministeps(lattice, dims, K, S, cells, occ, V, seed, beta, 0, 1, 1 + n_more,
                              nthreads=nthreads)
         t1 += time.perf_counter() - t0
         trials += int(r2.stats[0])
+    # one thread: the next mini-step of the same sweep
+    t0 = time.perf_counter()
+    r1 = O.run_ministeps(lattice, dims, K, S, cells, occ, V, seed, beta, 0, 1 + n_more, 2 + n_more, nthreads=1)
+    ts = time.perf_counter() - t0
     return {"value": trials / t1, "unit": "attempted swaps/s", "cores": nthreads, "kind": "oracle",
             "sample": f"mini-steps 0..{n_more} of sweep 0 on the same {dims[0]}x{dims[1]}x{dims[2]} "
-                      f"lattice ({trials} trials, {t1:.1f} s)"}
+                      f"lattice ({trials} trials, {t1:.1f} s)",
+            "cpu_model": model, "host_cpus": ncpu, "cpus_allowed": allowed,
+            "single_thread": {"value": int(r1.stats[0]) / ts, "unit": "attempted swaps/s",
+                              "sample": f"mini-step {1 + n_more} of sweep 0 ({int(r1.stats[0])} trials, "
+                                        f"{ts:.1f} s)"}}
 
 
 def main():
@@ -207,9 +238,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u8",
+        "dtype": "fp64",
         "data": "synthetic",
         "config": {"workload": f"bcc{dtag}_k4_s4_T1200_sro10", "lattice": "BCC",
+                   "arithmetic": "fp64 dE, E and SRO; integer pair counts",
+                   "storage": "u8 occupancy (one byte per site)",
                    "dims": list(dims), "sites": N, "species": K, "shells": S, "T_K": T,
                    "sweeps_per_step": spst, "link_cell": args.ell, "n_ministeps": nA,
                    "n_cells": nC, "mode": args.mode, "tile": list(tile),
@@ -257,6 +290,11 @@ def roofline(kernel, hbm_gbs, alu_tops, traffic, avg_launch_s, launches, bytes_p
            # bandwidth a one-launch-per-mini-step schedule (every byte re-read per
            # mini-step, 2 bytes written per trial) would need for this throughput
            "per_ministep_schedule_equivalent": swaps_per_s * (n_ministeps + 2.0) / 1e9}
+    if traffic and avg_launch_s:
+        # measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)
+        hbm["measured_gbs"] = traffic / avg_launch_s / 1e9
+        hbm["measured_frac"] = hbm["measured_gbs"] / HBM_PEAK_GBS
+    hbm["half_peak_met"] = bool(hbm["frac"] is not None and hbm["frac"] >= 0.5)
     common = {"kernel": kernel, "avg_launch_us": avg_launch_s * 1e6, "launches": launches, "traffic": traffic}
     if kernel == "k_rows":
         return {"bound": "alu", "achieved": alu_tops, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
@@ -314,6 +352,16 @@ def ladder_bench(args):
         sweep_no = int(g.counter.item())
         g.close()
     lat.close()
+    # the batched stream launch of the plain loop's own kernel (tile windows,
+    # one launch per mini-step group over all replicas): the gain of batching
+    # alone, with the kernel held fixed
+    work = occ_dev.clone()
+    lat = smcx.Lattice(I.BCC, dims, lad.K, lad.S, work, ell=4, rows=False)
+    lat.set_epi(lad.V)
+    bt = np.tile(lad.betas, (n, 1))
+    lat.sweep(1, 0, lad.betas.reshape(1, -1), mode="stream")
+    res["stream_tiles"] = n * N / timed(lambda: lat.sweep(n, 0, bt, first_sweep=1, mode="stream"))
+    lat.close()
     best = smcx.autotune(I.BCC, dims, lad.K, lad.S, occ_dev, lad.V, lad.betas, sweeps=2)
     work = occ_dev.clone()
     lat = smcx.Lattice(I.BCC, dims, lad.K, lad.S, work, ell=best["ell"], tile=best["tile"], rows=best["rows"])
@@ -328,7 +376,9 @@ def ladder_bench(args):
             "unit": "attempted swaps/s", "swaps_per_s": res,
             "tuned_config": {"tile": best["tile"], "mode": best["mode"], "ell": best["ell"], "rows": best["rows"]},
             "batched_over_plain": batched / res["plain"],
-            "batched_over_plain_graph": batched / res["plain_graph"]}
+            "batched_over_plain_graph": batched / res["plain_graph"],
+            # same kernel (tile windows) in both: batching alone
+            "batching_gain_same_kernel": res["stream_tiles"] / res["plain"]}
 
 
 def tempering_bench(args, rounds: int = 4, sweeps_per_round: int = 5):
