@@ -93,5 +93,7 @@ def forced_exchange_tie(E, beta_slot, rep_at, seed: int, round_: int, pair: int)
     u = exchange_draw(seed, round_, pair)
     bs[pair + 1] = bs[pair] - math.log(u) / dEab
     x = (bs[pair] - bs[pair + 1]) * dEab
-    assert x < 0.0 and abs(u - math.exp(x)) < 1e-3 * TIE_WINDOW, (u, x)
+    # x carries the rounding of the beta difference (a few 1e-14 relative);
+    # well inside the window, where either side's exp rounding cannot reach
+    assert x < 0.0 and abs(u - math.exp(x)) < 0.1 * TIE_WINDOW, (u, x)
     return bs, u, x
