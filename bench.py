@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--no-ladder", action="store_true",
                     help="skip the batched-ladder vs plain-loop comparison")
     ap.add_argument("--ladder-sweeps", type=int, default=20)
+    ap.add_argument("--legs", type=str, default="all",
+                    help="comma list of legs to run, for profiling one at a time: main (the BCC lattice "
+                         "above), ladder, tempering, anneal, qsro, fcc128, backward, clusters, cpu; "
+                         "the JSON line is printed only when main runs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--summarize", nargs="+", metavar="ARG",
@@ -142,6 +146,10 @@ def main():
     if args.summarize:
         summarize(args)
         return
+    legs = set(args.legs.split(",")) if args.legs != "all" else None
+    if legs is not None and "main" not in legs:
+        side_legs(args, legs)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus N > 1 is not supported", file=sys.stderr)
         sys.exit(2)
@@ -162,7 +170,7 @@ def main():
     tile = tuple(int(x) for x in args.tile.split(","))
     print(f"[bench] generating {N} sites", file=sys.stderr, flush=True)
     occ = I.occupancy_device(I.equiatomic(K, N), seed=0)
-    occ_host = occ.cpu().numpy() if not args.no_cpu_baseline else None
+    occ_host = occ.cpu().numpy() if not args.no_cpu_baseline and (legs is None or "cpu" in legs) else None
     lat = smcx.Lattice(lattice, dims, K, S, occ, ell=args.ell, tile=tile, double_buffer=args.double_buffer,
                        rows=not args.tiles)
     lat.set_epi(V)
@@ -253,28 +261,33 @@ def main():
                              trials_per_launch, ops, value, nA),
         "wall_s": wall,
     }
+    want = lambda name: legs is None or name in legs
     if not args.no_ladder:
-        print("[bench] ladder", file=sys.stderr, flush=True)
-        out["ladder"] = ladder_bench(args)
-        print("[bench] tempering", file=sys.stderr, flush=True)
-        out["tempering"] = tempering_bench(args)
-        print("[bench] anneal", file=sys.stderr, flush=True)
-        out["anneal"] = anneal_bench(args)
-        print("[bench] qsro", file=sys.stderr, flush=True)
-        out["qsro"] = qsro_bench(args)
-        print("[bench] fcc128", file=sys.stderr, flush=True)
-        out["fcc128"] = fcc128_bench(args)
-        print("[bench] backward", file=sys.stderr, flush=True)
-        out["backward"] = backward_bench(args)
-    if not args.no_ladder:
-        print("[bench] clusters", file=sys.stderr, flush=True)
-        out["clusters"] = clusters_bench(lat, N)
-    if not args.no_cpu_baseline:
+        for name, fn in (("ladder", ladder_bench), ("tempering", tempering_bench), ("anneal", anneal_bench),
+                         ("qsro", qsro_bench), ("fcc128", fcc128_bench), ("backward", backward_bench)):
+            if want(name):
+                print(f"[bench] {name}", file=sys.stderr, flush=True)
+                out[name] = fn(args)
+        if want("clusters"):
+            print("[bench] clusters", file=sys.stderr, flush=True)
+            out["clusters"] = clusters_bench(lat, N)
+    if not args.no_cpu_baseline and want("cpu"):
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(lattice, dims, K, S, cells, occ_host, V, seed, beta,
                                            args.cpu_seconds)
     lat.close()
     print(json.dumps(out), flush=True)
+
+
+def side_legs(args, legs):
+    """The workloads beside the headline one, each alone (for profiling)."""
+    out = {}
+    for name, fn in (("ladder", ladder_bench), ("tempering", tempering_bench), ("anneal", anneal_bench),
+                     ("qsro", qsro_bench), ("fcc128", fcc128_bench), ("backward", backward_bench)):
+        if name in legs:
+            print(f"[bench] {name}", file=sys.stderr, flush=True)
+            out[name] = fn(args)
+    print(json.dumps({"legs": out}), flush=True)
 
 
 def roofline(kernel, hbm_gbs, alu_tops, traffic, avg_launch_s, launches, bytes_per_launch, trials_per_launch,
