@@ -160,6 +160,23 @@ int smcx_workspace_size(const smcx_desc *desc, size_t *bytes);
 int smcx_lattice_init(smcx_lattice **out, const smcx_desc *desc, uint8_t *occ_dev, void *ws_dev,
                       size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * handle as smcx_lattice_init, with the workspace taken from a static array
+ * inside the library instead of a caller buffer.  Each device the library
+ * runs on holds its own array of 64 MiB (SMCX_STATIC_WORKSPACE_BYTES) until
+ * the process ends; descriptions whose smcx_workspace_size exceeds it are
+ * rejected with SMCX_E_WORKSPACE.  Nothing is allocated: the tables are
+ * uploaded with asynchronous copies on `stream`, which is synchronised.
+ * occ_dev as for smcx_lattice_init (caller-owned, every value < K).
+ * Every handle made by this call on one device shares that device's array:
+ * a later call on the device takes it over, after which the earlier handle's
+ * calls fail with SMCX_E_INVALID_ARG (destroy it as usual), and calls through
+ * such handles that overlap in time on one device race.  Errors: as for
+ * smcx_lattice_init, SMCX_E_WORKSPACE when the description does not fit. */
+#define SMCX_STATIC_WORKSPACE_BYTES (64u << 20)
+int smcx_lattice_init_static(smcx_lattice **out, const smcx_desc *desc, uint8_t *occ_dev, void *stream);
+
 int smcx_lattice_destroy(smcx_lattice *h);
 
 /* Partition actually used by replica r: ncell_out[3] cells per axis and the

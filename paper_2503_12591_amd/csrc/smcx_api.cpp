@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -445,6 +446,7 @@ struct smcx_lattice {
     const void* k_persistent = nullptr;
     const void* k_rows = nullptr;
     int rows_wgs = 8;
+    int static_dev = -1;  // device whose static workspace this handle uses, else -1
 };
 
 namespace {
@@ -551,9 +553,21 @@ int pack_all(smcx_lattice* h, bool unpack, bool planar, hipStream_t st)
     return SMCX_OK;
 }
 
+// The handle that currently owns each device's static workspace (a later
+// smcx_lattice_init_static on the same device takes it over).
+std::mutex g_static_mu;
+const smcx_lattice* g_static_owner[kMaxDevices] = {};
+
 int check_handle(const smcx_lattice* h)
 {
     if (!h) return fail(SMCX_E_INVALID_ARG, "handle is NULL");
+    if (h->static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (g_static_owner[h->static_dev] != h)
+            return fail(SMCX_E_INVALID_ARG,
+                        "the static workspace of this handle's device was taken over by a later "
+                        "smcx_lattice_init_static; this handle is no longer usable");
+    }
     return SMCX_OK;
 }
 
@@ -761,9 +775,43 @@ int smcx_lattice_init(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_de
     return SMCX_OK;
 }
 
+int smcx_lattice_init_static(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_dev, void* stream)
+{
+    if (!out) return fail(SMCX_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    if (int rc = smcx_workspace_size(desc, &need)) return rc;
+    if (need > kStaticWorkspaceBytes)
+        return fail(SMCX_E_WORKSPACE, "this description needs " + std::to_string(need) +
+                                          " bytes of workspace; the static workspace holds " +
+                                          std::to_string(kStaticWorkspaceBytes) +
+                                          " (pass a workspace to smcx_lattice_init instead)");
+    int dev = 0;
+    SMCX_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SMCX_E_UNSUPPORTED, "device ordinal beyond the static workspaces");
+    void* ws = nullptr;
+    SMCX_HIP(static_workspace(&ws));
+    {
+        // the tables below overwrite the workspace: an earlier handle on this
+        // device is unusable from here on
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static_owner[dev] = nullptr;
+    }
+    const int rc = smcx_lattice_init(out, desc, occ_dev, ws, kStaticWorkspaceBytes, stream);
+    if (rc != SMCX_OK) return rc;
+    (*out)->static_dev = dev;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static_owner[dev] = *out;
+    return SMCX_OK;
+}
+
 int smcx_lattice_destroy(smcx_lattice* h)
 {
     if (!h) return SMCX_OK;
+    if (h->static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (g_static_owner[h->static_dev] == h) g_static_owner[h->static_dev] = nullptr;
+    }
     for (auto& pr : h->pending) {
         hipEventDestroy(pr.first);
         hipEventDestroy(pr.second);

@@ -21,6 +21,10 @@ constexpr int kMaxZ1 = 12;
 constexpr int kMaxSumZ = 54;
 constexpr int kBlock = 256;
 constexpr int kMaxRowBlock = 1024;  // row kernel: several x-rows of link cells per workgroup
+// Static workspace of smcx_lattice_init_static (bytes, per device) and the
+// device ordinals it serves.
+constexpr size_t kStaticWorkspaceBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
 
 // ---------------------------------------------------------------------------
 // Geometry.  Positions are in half lattice constants.  Coordination shells are

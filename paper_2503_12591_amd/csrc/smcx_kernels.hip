@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "smcx_internal.h"
@@ -2442,6 +2443,36 @@ hipError_t launch_pair_counts(int lattice, int K, int S, const uint8_t* occ, int
         else hipLaunchKernelGGL((k_pair_counts<SMCX_FCC, 8>), g, b, 0, st, occ, N, L[0], L[1], L[2], K, S, cells_per_block, counts);
     }
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Static workspace for smcx_lattice_init_static: a file-scope device array, so
+// that a caller that cannot allocate device memory still gets a workspace.
+// Every device holds its own copy at its own address, resolved here once per
+// device (that device current) with hipGetSymbolAddress; host code passes
+// that address on, never the array's name, which in host code is only a
+// stand-in for the symbol.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[kStaticWorkspaceBytes];
+
+hipError_t static_workspace(void** ptr)
+{
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace smcx

@@ -22,6 +22,9 @@ hipError_t launch_advance_counter(uint32_t* counter, uint32_t n, hipStream_t st)
 hipError_t launch_pair_counts(int lattice, int K, int S, const uint8_t* occ, int64_t N, const int32_t* L,
                               int B, int64_t* counts, hipStream_t st);
 hipError_t launch_energy(const int64_t* C, const double* V, int R, int SKK, double* E, hipStream_t st);
+// Device address of the static workspace on the current device (looked up
+// once per device with that device current).
+hipError_t static_workspace(void** ptr);
 hipError_t launch_energy_grad(const int64_t* C, const double* g, int B, int SKK, double* grad, hipStream_t st);
 // Largest qSRO affected set a trial can have (entries of its LDS terms).
 constexpr int kQsroMaxAff = 256;

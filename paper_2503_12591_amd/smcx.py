@@ -31,6 +31,7 @@ EXPORTS = [
     "smcx_graph_launch", "smcx_graph_destroy", "smcx_timing_enable", "smcx_timing_read",
     "smcx_energy_dev", "smcx_exchange", "smcx_anneal", "smcx_local_energy", "smcx_clusters",
     "smcx_set_qsro", "smcx_sweep_qsro", "smcx_energy_of_counts", "smcx_energy_grad",
+    "smcx_lattice_init_static",
 ]
 
 
@@ -63,6 +64,7 @@ def lib():
     L.smcx_min_cell_edge.argtypes = [i32, i32]
     L.smcx_workspace_size.argtypes = [C.POINTER(Desc), C.POINTER(sz)]
     L.smcx_lattice_init.argtypes = [C.POINTER(p), C.POINTER(Desc), p, p, sz, p]
+    L.smcx_lattice_init_static.argtypes = [C.POINTER(p), C.POINTER(Desc), p, p]
     L.smcx_lattice_destroy.argtypes = [p]
     L.smcx_get_schedule.argtypes = [p, i32, p, p, p]
     L.smcx_set_epi.argtypes = [p, p, p]
@@ -132,7 +134,8 @@ class Lattice:
     """
 
     def __init__(self, lattice: int, dims, K: int, S: int, occ, ell=None, cells=None,
-                 tile=(0, 0, 0), double_buffer: bool = False, rows: bool = True):
+                 tile=(0, 0, 0), double_buffer: bool = False, rows: bool = True,
+                 static_workspace: bool = False):
         torch = _torch()
         self.torch = torch
         dims = np.asarray(dims, dtype=np.int32).reshape(-1, 3)
@@ -171,12 +174,17 @@ class Lattice:
         self._desc = d
         nbytes = C.c_size_t(0)
         _check(lib().smcx_workspace_size(C.byref(d), C.byref(nbytes)))
-        self.ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device="cuda")
-        base = self.ws.data_ptr()
-        self._ws_ptr = (base + 255) & ~255
         h = C.c_void_p()
-        _check(lib().smcx_lattice_init(C.byref(h), C.byref(d), _ptr(self.occ), C.c_void_p(self._ws_ptr),
-                                       nbytes.value, _stream(torch)))
+        if static_workspace:
+            # the library's own per-device workspace (smcx_lattice_init_static)
+            self.ws = None
+            _check(lib().smcx_lattice_init_static(C.byref(h), C.byref(d), _ptr(self.occ), _stream(torch)))
+        else:
+            self.ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device="cuda")
+            base = self.ws.data_ptr()
+            self._ws_ptr = (base + 255) & ~255
+            _check(lib().smcx_lattice_init(C.byref(h), C.byref(d), _ptr(self.occ), C.c_void_p(self._ws_ptr),
+                                           nbytes.value, _stream(torch)))
         self.h = h
         self.ws_bytes = int(nbytes.value)
         self.counts = torch.zeros(self.R * S * K * K, dtype=torch.int64, device="cuda")
