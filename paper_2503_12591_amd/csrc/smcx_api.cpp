@@ -99,7 +99,7 @@ struct Plan {
     std::vector<Replica> reps;
     int LP, WY, WZ;
     LdsLayout lds;
-    size_t off_reps, off_origins, off_tileoff, off_offP, off_offB, off_pd, off_D, off_V, off_misc, off_pad, total;
+    size_t off_reps, off_origins, off_tileoff, off_offP, off_offB, off_pd, off_D, off_Q, off_V, off_misc, off_pad, total;
     // qSRO model: affected-set and neighbour tables, V, W, Z
     size_t off_qaff, off_qnbr, off_qV, off_qW, off_qZ, off_qslots;
     int qnaff;  // largest affected set
@@ -388,6 +388,7 @@ int make_plan(const smcx_desc* d, Plan& P)
     P.off_offB = o; o = align256(o + sizeof(int32_t) * P.m * P.Z1);
     P.off_pd = o; o = align256(o + 4 * P.m * P.Z1);
     P.off_D = o; o = align256(o + sizeof(double) * P.K * P.K * P.S * P.K);
+    P.off_Q = o; o = align256(o + sizeof(int32_t) * (qtab_entries(P.K, P.S) + 2));
     P.off_V = o; o = align256(o + sizeof(double) * P.S * P.K * P.K);
     P.off_misc = o; o = align256(o + 256);
     P.off_qaff = o; o = align256(o + sizeof(int32_t) * P.m * P.Z1 * (1 + kQsroMaxAff));
@@ -436,6 +437,7 @@ struct smcx_lattice {
     bool qsro_set = false;
     std::vector<double> V;       // [S][K][K]
     std::vector<double> Dhost;   // [S][K][K][K]: D[s][t][p][q]
+    std::vector<int32_t> Qhost;  // D in integer units, the bias sums, the unit and the error bound (float bits)
     std::vector<int64_t> counts_host;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
@@ -462,6 +464,7 @@ SweepArgs base_args(smcx_lattice* h)
     a.offB = (const int32_t*)(h->ws + P.off_offB);
     a.pdisp = (const int8_t*)(h->ws + P.off_pd);
     a.Dtab = (const double*)(h->ws + P.off_D);
+    a.Qtab = (const int32_t*)(h->ws + P.off_Q);
     a.ws = h->ws;
     a.R = P.R;
     a.K = P.K;
@@ -473,6 +476,7 @@ SweepArgs base_args(smcx_lattice* h)
     a.WY = P.WY;
     a.WZ = P.WZ;
     a.lds_d = P.lds.d_off;
+    a.lds_q = P.lds.q_off;
     a.lds_offp = P.lds.offp_off;
     a.lds_offb = P.lds.offb_off;
     a.lds_pd = P.lds.pd_off;
@@ -500,6 +504,7 @@ SweepArgs row_args(smcx_lattice* h)
     a.WY = P.rWY;
     a.WZ = P.rWZ;
     a.lds_d = P.rlds.d_off;
+    a.lds_q = P.rlds.q_off;
     a.lds_offp = P.rlds.offp_off;
     a.lds_offb = P.rlds.offb_off;
     a.lds_pd = P.rlds.pd_off;
@@ -858,8 +863,42 @@ int smcx_set_epi(smcx_lattice* h, const double* V, void* stream)
             for (int s = 0; s < S; ++s)
                 for (int t = 0; t < K; ++t)
                     h->Dhost[((s * K + t) * K + p) * K + q] = V[(s * K + q) * K + t] - V[(s * K + p) * K + t];
+    // Integer screen of dE (the kernels' first test): every D rounded to a
+    // multiple of 2^-k, the largest k with all |D| 2^k below 2^23 (24-bit
+    // signed operands), plus for each (p, q) the sum of half * those integers
+    // (the counters' field bias), modulo 2^32.  A trial's integer sum is then
+    // within sum_t |c_t| 2^-(k+1) <= (sum_s Z_s) 2^-k of sum c D, which is
+    // within a few ulps of the binary64 dE; qeps bounds both.
+    {
+        double maxD = 0.0;
+        for (double v : h->Dhost) maxD = std::max(maxD, std::fabs(v));
+        int kq = 0;
+        if (maxD > 0.0) {
+            kq = (int)std::floor(std::log2(8388607.0 / maxD));
+            while (std::ldexp(maxD, kq) > 8388607.0) --kq;
+            kq = std::max(-100, std::min(100, kq));
+        }
+        const int half = K == 5 ? 32 : 128;
+        const size_t nD = h->Dhost.size();
+        h->Qhost.assign((size_t)qtab_entries(K, S) + 2, 0);
+        for (size_t i = 0; i < nD; ++i) h->Qhost[i] = (int32_t)std::nearbyint(std::ldexp(h->Dhost[i], kq));
+        for (int p = 0; p < K; ++p)
+            for (int q = 0; q < K; ++q) {
+                int64_t b = 0;
+                for (int s = 0; s < S; ++s)
+                    for (int t = 0; t < K; ++t) b += (int64_t)half * h->Qhost[((s * K + t) * K + p) * K + q];
+                h->Qhost[nD + p * K + q] = (int32_t)(uint32_t)(uint64_t)b;
+            }
+        int sumZ = 0;
+        for (int s = 0; s < S; ++s) sumZ += kGeom[P.lattice].Z[s];
+        const float qscale = (float)std::ldexp(1.0, -kq);
+        const float qeps = (float)((sumZ * std::ldexp(1.0, -kq) + 1e-12 * (1.0 + 64.0 * maxD)) * 1.001);
+        std::memcpy(&h->Qhost[(size_t)qtab_entries(K, S)], &qscale, 4);
+        std::memcpy(&h->Qhost[(size_t)qtab_entries(K, S) + 1], &qeps, 4);
+    }
     hipStream_t st = (hipStream_t)stream;
     SMCX_HIP(hipMemcpyAsync(h->ws + P.off_D, h->Dhost.data(), sizeof(double) * h->Dhost.size(), hipMemcpyHostToDevice, st));
+    SMCX_HIP(hipMemcpyAsync(h->ws + P.off_Q, h->Qhost.data(), sizeof(int32_t) * h->Qhost.size(), hipMemcpyHostToDevice, st));
     SMCX_HIP(hipMemcpyAsync(h->ws + P.off_V, h->V.data(), sizeof(double) * h->V.size(), hipMemcpyHostToDevice, st));
     SMCX_HIP(hipStreamSynchronize(st));
     h->epi_set = true;

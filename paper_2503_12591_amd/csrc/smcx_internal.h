@@ -224,6 +224,8 @@ struct SweepArgs {
     const int32_t* offB;       // [m][Z1] partner offset relative to the active site
     const int8_t* pdisp;       // [m][Z1][4] partner cell displacement and basis
     const double* Dtab;        // [S][K][K][K]: D[s][t][p][q] = V_s[q][t] - V_s[p][t]
+    const int32_t* Qtab;       // [S][K][K][K] D in integer units, [K][K] bias sums, then the unit and
+                               // the error bound as float bits (qtab_entries + 2 words)
     uint8_t* ws;               // workspace base (padded copies)
     const double* beta;        // beta[js * beta_stride + r]
     int64_t* stats;            // [R][3]
@@ -238,7 +240,7 @@ struct SweepArgs {
     int32_t R, K, S, Z1, sumZ;
     int32_t T[3];              // tile shape (link cells)
     int32_t LP, WY, WZ;        // LDS window: row pitch, rows per plane, planes
-    int32_t lds_d, lds_offp, lds_offb, lds_pd, lds_win;  // dynamic-LDS byte offsets
+    int32_t lds_d, lds_q, lds_offp, lds_offb, lds_pd, lds_win;  // dynamic-LDS byte offsets
     int32_t win_bytes;         // one window buffer
     int32_t nbuf;              // window buffers: 2 = next tile streams in during the trials, 1 = staged in turn
     int32_t g;                 // mini-step (stream / plain launches)
@@ -252,8 +254,12 @@ struct SweepArgs {
 
 // Dynamic LDS layout helpers (byte offsets, 16-aligned).
 struct LdsLayout {
-    int d_off, offp_off, offb_off, pd_off, win_off, win_bytes, total;
+    int d_off, q_off, offp_off, offb_off, pd_off, win_off, win_bytes, total;
 };
+
+// Entries of the integer dE table: [S][K][K][K] terms, then [K][K] bias sums
+// (two float words follow them in memory: the unit and the error bound).
+inline int qtab_entries(int K, int S) { return S * K * K * K + K * K; }
 
 inline LdsLayout lds_layout(int lattice, int K, int S, int Z1, int sumZ, int win_bytes, int nbuf)
 {
@@ -262,7 +268,9 @@ inline LdsLayout lds_layout(int lattice, int K, int S, int Z1, int sumZ, int win
     LdsLayout L{};
     int o = 0;
     L.d_off = o;    o = al(o + 8 * K * K * S * K);
-    L.offp_off = o; o = al(o + 2 * m * Z1 * sumZ);
+    L.q_off = o;    o = al(o + 4 * qtab_entries(K, S));
+    // the partner-neighbour offset table serves FCC windows only
+    L.offp_off = o; o = al(o + (lattice == SMCX_FCC ? 2 * m * Z1 * sumZ : 0));
     L.offb_off = o; o = al(o + 4 * m * Z1);
     L.pd_off = o;   o = al(o + 4 * m * Z1);
     L.win_off = o;

@@ -184,21 +184,6 @@ constexpr Nb min_components(const Geometry& G, int b)
     return r;
 }
 
-// Smallest (lo) and largest (hi) cell displacement, over the y and z axes
-// and every basis site, of a site's nearest neighbours: the rows a swap
-// partner can lie in, relative to the active site's row.
-constexpr int partner_reach(const Geometry& G, bool hi)
-{
-    int r = 0;
-    for (int b = 0; b < G.m; ++b)
-        for (int n = 0; n < G.Z[0]; ++n) {
-            const Nb nb = nb_of(G, b, G.v[0][n][0], G.v[0][n][1], G.v[0][n][2]);
-            const int a = hi ? (nb.dy > nb.dz ? nb.dy : nb.dz) : (nb.dy < nb.dz ? nb.dy : nb.dz);
-            r = hi ? (a > r ? a : r) : (a < r ? a : r);
-        }
-    return r;
-}
-
 template <int LAT, int B, bool PLANAR, typename CT>
 __device__ __forceinline__ void count_uniform(const uint8_t* win, int base, int LP, int PL, int CP, int S,
                                               CT (&A)[kMaxShells])
@@ -261,6 +246,9 @@ __device__ __forceinline__ void count_table(const uint8_t* win, int base, const 
 
 struct Lds {
     const double* D;
+    const int32_t* Q;  // integer dE terms [S][K][K][K], then bias sums [K][K]
+    float qscale;      // value of one integer unit (a power of two)
+    float qeps;        // bound on |integer dE - binary64 dE| before the float conversion
     const int16_t* offP;
     const int32_t* offB;
     const int8_t* pd;
@@ -270,6 +258,12 @@ __device__ __forceinline__ Lds lds_ptrs(const SweepArgs& A, uint8_t* smem)
 {
     Lds l;
     l.D = (const double*)(smem + A.lds_d);
+    l.Q = (const int32_t*)(smem + A.lds_q);
+    // read at run time, like the tables, so that a captured graph follows smcx_set_epi
+    using CI = const __attribute__((address_space(4))) int32_t;
+    const int nq = A.S * A.K * A.K * A.K + A.K * A.K;
+    l.qscale = __int_as_float(((CI*)A.Qtab)[nq]);
+    l.qeps = __int_as_float(((CI*)A.Qtab)[nq + 1]);
     l.offP = (const int16_t*)(smem + A.lds_offp);
     l.offB = (const int32_t*)(smem + A.lds_offb);
     l.pd = (const int8_t*)(smem + A.lds_pd);
@@ -284,6 +278,9 @@ __device__ void load_tables(const SweepArgs& A, uint8_t* smem)
     double* D = (double*)(smem + A.lds_d);
     const int nD = A.K * A.K * A.S * A.K;
     for (int i = threadIdx.x; i < nD; i += blockDim.x) D[i] = A.Dtab[i];
+    int32_t* Q = (int32_t*)(smem + A.lds_q);
+    const int nQ = nD + A.K * A.K;
+    for (int i = threadIdx.x; i < nQ; i += blockDim.x) Q[i] = A.Qtab[i];
     if constexpr (LAT == SMCX_FCC) {
         int16_t* P = (int16_t*)(smem + A.lds_offp);
         const int nP = m * A.Z1 * A.sumZ;
@@ -635,57 +632,110 @@ __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& re
     const int p8 = L.p8, q8 = L.q8, k = L.k;
     // species were checked < K at init; the clamp keeps table reads in bounds regardless
     const int p = min(species_of(p8, EN::F), K - 1), q = min(species_of(q8, EN::F), K - 1);
-    // D[s][t][p][q]: the lanes' (p, q) entries of one term lie in one
-    // K*K*8-byte block, so their reads do not collide in LDS banks
-    const double* Dp = T.D + (p * K + q);
-    // the sum starts from the first product rather than from +0.0 + it: the
-    // two differ only in the sign of a zero sum, and dE <= 0 accepts either
-    double dE;
+    // the per-shell count differences, fields biased by `half`
+    CT dsh[kMaxShells];
+#pragma unroll
+    for (int s = 0; s < kMaxShells; ++s) {
+        // images of the partner inside shell s (1, 0, 0, 0 unless an edge is 2)
+        const CT mu = Geo::may_alias && rep.alias ? (CT)rep.mult[s][k] : (CT)(s == 0 ? 1 : 0);
+        dsh[s] = s < S ? L.Ca[s] + EN::bias - L.Cb[s] + (mu << p8) - (mu << q8) : (CT)0;
+    }
+    // Screen: dE in integers.  Qtab holds every D[s][t][p][q] rounded to a
+    // multiple of qscale (24-bit signed), so sum_t (c_t + half) Q - bias, bias
+    // = half sum Q, is sum_t c_t Q exactly (modulo 2^32, and it fits in 32
+    // bits), within qeps / qscale units of the binary64 dE.  It settles the
+    // decision whenever that uncertainty cannot change it; otherwise the
+    // binary64 sum and test below decide, as they always would.
+    const int32_t* Qp = T.Q + (p * K + q);
+    uint32_t qacc = 0u - (uint32_t)T.Q[S * K * K * K + p * K + q];
 #pragma unroll
     for (int s = 0; s < kMaxShells; ++s) {
         if (s < S) {
-            // images of the partner inside shell s (1, 0, 0, 0 unless an edge is 2)
-            const CT mu = Geo::may_alias && rep.alias ? (CT)rep.mult[s][k] : (CT)(s == 0 ? 1 : 0);
-            const CT d = L.Ca[s] + EN::bias - L.Cb[s] + (mu << p8) - (mu << q8);
 #pragma unroll
             for (int tt = 0; tt < EN::KP; ++tt) {
                 if (tt < K) {
-                    const int c = (int)((d >> (EN::F * tt)) & EN::mask) - EN::half;
-                    const double term = (double)c * Dp[(s * K + tt) * K * K];
-                    dE = s == 0 && tt == 0 ? term : dE + term;
+                    const int u = (int)((dsh[s] >> (EN::F * tt)) & EN::mask);
+                    qacc += (uint32_t)__mul24(u, Qp[(s * K + tt) * K * K]);
                 }
             }
         }
     }
-    bool acc;
+    const float e = (float)(int32_t)qacc * T.qscale;
+    const float eps = T.qeps + fabsf(e) * 0x1p-22f;
+    const float bf = (float)beta;
+    bool acc = false;
     bool tie = false;
-    if (dE <= 0.0) {
-        acc = true;
-    } else {
-        const double x = beta * dE;
-        // A float estimate settles u < exp(-x) whenever u lies farther from
-        // it than the estimate's error: the binary64 test then gives the same
-        // answer and the trial is no near-tie.  u = (w1 2^21 + (w2 >> 11))
-        // 2^-53 lies in [w1 2^-32, (w1 + 1) 2^-32).  For x <= 30, rounding x
-        // and x log2(e) to float moves the exponent by < 8e-6, so exp2 is off
-        // by < 6e-6 relative (plus an ulp or two of v_exp_f32); the margin
-        // is 1e-4 relative plus 1e-9 for u's truncation and rounding.
-        bool settled = false;
-        if (x > 30.0) {
-            // exp(-x) < 1e-13, while u >= 2^-32 unless w1 == 0
+    bool settled = true;
+    if (e <= -eps) {
+        acc = true;  // dE <= e + eps <= 0
+    } else if (e > eps && bf >= 0.0f && bf * eps < 0.25f) {
+        // dE > 0 and beta dE lies in [bf (e - eps), bf (e + eps)] up to float
+        // rounding.  u = (w1 2^21 + (w2 >> 11)) 2^-53 lies in [w1 2^-32,
+        // (w1 + 1) 2^-32).  With y = bf eps <= 1/4, exp(-beta dE) is within
+        // a factor exp(+-y) (<= 1.14 y relative) of exp(-bf e), and the float
+        // estimate of that is within 2e-5 relative for beta dE <= 31, so a
+        // margin of 1e-4 + 1.2 y relative plus 1e-9 for u's truncation
+        // settles u < exp(-beta dE) exactly, and such a trial is no near-tie.
+        if (bf * (e - eps) * (1.0f - 0x1p-20f) > 30.0f) {
+            // exp(-beta dE) < 1e-13, while u >= 2^-32 unless w1 == 0
             settled = L.w1 != 0;
-            acc = false;
         } else {
             const float uf = (float)L.w1 * 0x1p-32f;
-            const float Pf = __builtin_amdgcn_exp2f((float)x * -1.44269504f);
-            settled = fabsf(uf - Pf) > 1e-4f * Pf + 1e-9f;
+            const float Pf = __builtin_amdgcn_exp2f(bf * e * -1.44269504f);
+            settled = fabsf(uf - Pf) > (1e-4f + 1.2f * bf * eps) * Pf + 1e-9f;
             acc = uf < Pf;
         }
-        if (!settled) {
-            const double P = exp(-x);
-            const double u = (double)(((uint64_t)L.w1 << 21) | (uint64_t)(L.w2 >> 11)) * 0x1p-53;
-            acc = u < P;
-            tie = fabs(u - P) < 1e-12;
+    } else {
+        settled = false;
+    }
+    if (!settled) {
+        // the binary64 dE, s and t ascending; D[s][t][p][q]: the lanes' (p, q)
+        // entries of one term lie in one K*K*8-byte block, so their reads do
+        // not collide in LDS banks.  The sum starts from the first product
+        // rather than from +0.0 + it: the two differ only in the sign of a
+        // zero sum, and dE <= 0 accepts either.
+        const double* Dp = T.D + (p * K + q);
+        double dE;
+#pragma unroll
+        for (int s = 0; s < kMaxShells; ++s) {
+            if (s < S) {
+#pragma unroll
+                for (int tt = 0; tt < EN::KP; ++tt) {
+                    if (tt < K) {
+                        const int c = (int)((dsh[s] >> (EN::F * tt)) & EN::mask) - EN::half;
+                        const double term = (double)c * Dp[(s * K + tt) * K * K];
+                        dE = s == 0 && tt == 0 ? term : dE + term;
+                    }
+                }
+            }
+        }
+        if (dE <= 0.0) {
+            acc = true;
+        } else {
+            const double x = beta * dE;
+            // A float estimate settles u < exp(-x) whenever u lies farther
+            // from it than the estimate's error: the binary64 test then gives
+            // the same answer and the trial is no near-tie.  For x <= 30,
+            // rounding x and x log2(e) to float moves the exponent by < 8e-6,
+            // so exp2 is off by < 6e-6 relative (plus an ulp or two of
+            // v_exp_f32); the margin is 1e-4 relative plus 1e-9 for u's
+            // truncation and rounding.
+            bool fine = false;
+            if (x > 30.0) {
+                fine = L.w1 != 0;
+                acc = false;
+            } else {
+                const float uf = (float)L.w1 * 0x1p-32f;
+                const float Pf = __builtin_amdgcn_exp2f((float)x * -1.44269504f);
+                fine = fabsf(uf - Pf) > 1e-4f * Pf + 1e-9f;
+                acc = uf < Pf;
+            }
+            if (!fine) {
+                const double P = exp(-x);
+                const double u = (double)(((uint64_t)L.w1 << 21) | (uint64_t)(L.w2 >> 11)) * 0x1p-53;
+                acc = u < P;
+                tie = fabs(u - P) < 1e-12;
+            }
         }
     }
     if (tie) {
@@ -1077,53 +1127,94 @@ __device__ __forceinline__ void row_trials(int b0, int b1, const SweepArgs& A, c
     }
 }
 
-// Copy the window rows a row group's trials can have changed back to the
-// padded copy: for a row of link cells with an active site at (ya, za) on y
-// and z, the rows within a partner's reach of it on both axes, each to its
-// own row and to its halo images when it lies within H of a face.  Whole
-// padded rows go out, x-images included (the trials keep those current in the
-// window).  No other workgroup of the launch changes these rows (their cells'
-// active rows lie at least a cell edge away), so writing back bytes that did
-// not change is harmless.  The T0 lanes of the cell row share its rows, 16
-// bytes per lane and item.
+// Basis-planar row segments a row group's trials can write: for a cell row
+// whose active sites lie in row (ya, za), the active sites' own columns (every
+// basis site) in that row, and for every partner direction the partner's
+// column in the row it falls in.  Any other column of the rows around stays
+// as it was staged.  Worked out at compile time from the shell-1 vectors.
+struct WbSeg {
+    int dy, dz, col;
+};
+struct WbPlan {
+    int n;
+    WbSeg seg[4 * 2 * kMaxZ1];
+};
+
+constexpr WbPlan make_wb_plan(const Geometry& G)
+{
+    WbPlan P{};
+    P.n = 0;
+    auto add = [&P](int dy, int dz, int col) {
+        for (int i = 0; i < P.n; ++i)
+            if (P.seg[i].dy == dy && P.seg[i].dz == dz && P.seg[i].col == col) return;
+        P.seg[P.n].dy = dy;
+        P.seg[P.n].dz = dz;
+        P.seg[P.n].col = col;
+        ++P.n;
+    };
+    for (int b = 0; b < G.m; ++b) {
+        add(0, 0, b);
+        for (int k = 0; k < G.Z[0]; ++k) {
+            const Nb nb = nb_of(G, b, G.v[0][k][0], G.v[0][k][1], G.v[0][k][2]);
+            add(nb.dy, nb.dz, nb.bt);
+        }
+    }
+    return P;
+}
+
+// Copy the window row segments a row group's trials can have changed back to
+// the padded copy: each segment (a basis column of a row within a partner's
+// reach of the active row) to its own row and to its halo images when the row
+// lies within H of a y or z face.  A whole column goes out, x-images included
+// (the trials keep those current in the window).  No other workgroup of the
+// launch changes these rows (their cells' active rows lie at least a cell edge
+// away), so writing back bytes that did not change is harmless.  The T0 lanes
+// of the cell row share its segments, 16 bytes per lane and item.
 template <int LAT, class Geo>
 __device__ __forceinline__ void rows_writeback(const SweepArgs& A, const RepDev& rep, const TileGeom& tg, int lx,
                                                int T0, int ya, int za, uint8_t* pad, const uint8_t* win)
 {
-    constexpr Geometry G = kGeom[LAT];
-    constexpr int PLO = partner_reach(G, false), NP = partner_reach(G, true) - PLO + 1;
-    constexpr int NR = NP * NP;  // candidate rows: partners reach NP rows along y and along z
+    constexpr WbPlan W = make_wb_plan(kGeom[LAT]);
+    constexpr int NS = W.n;
     const int LP = Geo::LP(A), WY = Geo::WY(A);
-    const int n16 = rep.prowp >> 4;
+    const int cp = Geo::CP(rep), nc16 = cp >> 4;  // chunks of one basis column
     const int Ly = rep.L[1], Lz = rep.L[2];
     const int64_t prowp = rep.prowp, plane = (int64_t)rep.prows * prowp;
-    // g lanes per row, consecutive lanes on consecutive 16-byte chunks of one
-    // row, so the row's addresses are worked out once per lane; with fewer
-    // lanes than rows a lane takes rows lx, lx + T0, ...
-    const int g = T0 / NR;
+    // g lanes per segment, consecutive lanes on consecutive 16-byte chunks,
+    // so a segment's addresses are worked out once per lane; with fewer lanes
+    // than segments a lane takes segments lx, lx + T0, ...
+    const int g = T0 / NS;
     int d = lx, dstep = T0, c0 = 0, cstep = 1;
     if (g > 0) {
-        if (lx >= g * NR) return;
+        if (lx >= g * NS) return;
         d = lx / g;
-        dstep = NR;
+        dstep = NS;
         c0 = lx - d * g;
         cstep = g;
     }
-    for (; d < NR; d += dstep) {
-        const int y = ya + d % NP + PLO, z = za + d / NP + PLO;  // in [-1, L]
+    for (; d < NS; d += dstep) {
+        int dy = 0, dz = 0, col = 0;
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+            if (i == d) {
+                dy = W.seg[i].dy;
+                dz = W.seg[i].dz;
+                col = W.seg[i].col;
+            }
+        const int y = ya + dy, z = za + dz;  // in [-1, L]
         const int yr = y < 0 ? y + Ly : (y >= Ly ? y - Ly : y);
         const int zr = z < 0 ? z + Lz : (z >= Lz ? z - Lz : z);
         const int yi = yr < kHalo ? yr + Ly : (yr >= Ly - kHalo ? yr - Ly : yr);  // image, or yr itself
         const int zi = zr < kHalo ? zr + Lz : (zr >= Lz - kHalo ? zr - Lz : zr);
-        const uint8_t* src = win + ((z - tg.w0[2]) * WY + (y - tg.w0[1])) * LP + 16 * c0;
-        uint8_t* dst = pad + (zr + kHalo) * plane + (yr + kHalo) * prowp + 16 * c0;
-        const int64_t dy = (int64_t)(yi - yr) * prowp, dz = (int64_t)(zi - zr) * plane;  // images (0: none)
-        for (int c = c0; c < n16; c += cstep) {
+        const uint8_t* src = win + ((z - tg.w0[2]) * WY + (y - tg.w0[1])) * LP + col * cp + 16 * c0;
+        uint8_t* dst = pad + (zr + kHalo) * plane + (yr + kHalo) * prowp + col * cp + 16 * c0;
+        const int64_t ddy = (int64_t)(yi - yr) * prowp, ddz = (int64_t)(zi - zr) * plane;  // images (0: none)
+        for (int c = c0; c < nc16; c += cstep) {
             const uint4 v = *(const uint4*)src;
             *(uint4*)dst = v;
-            if (dy) *(uint4*)(dst + dy) = v;
-            if (dz) *(uint4*)(dst + dz) = v;
-            if (dy && dz) *(uint4*)(dst + dy + dz) = v;
+            if (ddy) *(uint4*)(dst + ddy) = v;
+            if (ddz) *(uint4*)(dst + ddz) = v;
+            if (ddy && ddz) *(uint4*)(dst + ddy + ddz) = v;
             src += 16 * cstep;
             dst += 16 * cstep;
         }
