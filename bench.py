@@ -68,6 +68,9 @@ def parse():
                          "the JSON line is printed only when main runs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--profile-name", type=str, default="",
+                    help="with --summarize trace: file stem and title of the summary (default: the "
+                         "benchmark lattice's sweep trace)")
     ap.add_argument("--summarize", nargs="+", metavar="ARG",
                     help="write profiles/ summaries from rocprofv3 csv output and exit: "
                          "'trace DIR CMD' (kernel-trace --stats) or "
@@ -665,7 +668,8 @@ def summarize(args):
         d, cmd = rest[0], " ".join(rest[1:])
         rows = _csv(d, "kernel_stats.csv")
         rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-        lines = [f"# rocprofv3 kernel trace: BCC {args.edge}^3 benchmark, link cell {args.ell}",
+        title = args.profile_name or f"BCC {args.edge}^3 benchmark, link cell {args.ell}"
+        lines = [f"# rocprofv3 kernel trace: {title}",
                  f"# command: {cmd}", "",
                  f"{'calls':>7} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_ms':>10} {'pct':>6}  kernel"]
         for r in rows:
@@ -675,7 +679,8 @@ def summarize(args):
             lines.append(f"{int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.1f} "
                          f"{float(r['MinNs']) / 1e3:10.1f} {float(r['MaxNs']) / 1e3:10.1f} "
                          f"{float(r['TotalDurationNs']) / 1e6:10.2f} {float(r['Percentage']):6.2f}  {name}")
-        with open(os.path.join(ROOT, "profiles", f"sweep_{tag}_kernel_trace.txt"), "w") as f:
+        stem = args.profile_name.replace(" ", "_") if args.profile_name else f"sweep_{tag}"
+        with open(os.path.join(ROOT, "profiles", f"{stem}_kernel_trace.txt"), "w") as f:
             f.write("\n".join(lines) + "\n")
     elif kind == "traffic":
         fd, wd, cfd, cwd, cmd = rest[0], rest[1], rest[2], rest[3], " ".join(rest[4:])
