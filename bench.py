@@ -761,6 +761,37 @@ def summarize(args):
                          f"{vals['SQ_LDS_BANK_CONFLICT'] / vals['SQ_LDS_IDX_ACTIVE']:.3f}")
         with open(os.path.join(ROOT, "profiles", f"{kname[2:]}_{tag}_sq_counters.txt"), "w") as f:
             f.write("\n".join(lines) + "\n")
+    elif kind == "counters-all":
+        # rest: counter-pass directories, then the command; every library
+        # kernel of the run, counters averaged per dispatch and per wave
+        dirs = [d for d in rest if os.path.isdir(d)]
+        cmd = " ".join(r for r in rest if r not in dirs)
+        per = {}
+        for d in dirs:
+            for r in _csv(d, "counter_collection.csv"):
+                if "smcx::" not in r["Kernel_Name"]:
+                    continue
+                k = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                per.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        title = args.profile_name or "library kernels"
+        lines = [f"# SQ counters of every library kernel: {title}",
+                 f"# command (one pass per group of counters): {cmd}",
+                 "# per dispatch: device totals averaged over the kernel's dispatches; per wave: divided by SQ_WAVES", ""]
+        for k in sorted(per):
+            c = {n: sum(v) / len(v) for n, v in per[k].items()}
+            nd = max(len(v) for v in per[k].values())
+            waves = c.get("SQ_WAVES", 0.0)
+            lines.append(f"{k}  ({nd} dispatches)")
+            for n in sorted(c):
+                pw = f"{c[n] / waves:14.2f}" if waves else ""
+                lines.append(f"  {n:26s} {c[n]:16.1f} {pw}")
+            if "SQ_LDS_BANK_CONFLICT" in c and c.get("SQ_LDS_IDX_ACTIVE"):
+                lines.append(f"  LDS bank-conflict cycles / LDS active cycles: "
+                             f"{c['SQ_LDS_BANK_CONFLICT'] / c['SQ_LDS_IDX_ACTIVE']:.3f}")
+            lines.append("")
+        stem = args.profile_name.replace(" ", "_") if args.profile_name else "kernels"
+        with open(os.path.join(ROOT, "profiles", f"{stem}_sq_counters.txt"), "w") as f:
+            f.write("\n".join(lines) + "\n")
     else:
         raise SystemExit(f"unknown summary kind {kind}")
 

@@ -224,6 +224,63 @@ __device__ __forceinline__ void count_uniform(const uint8_t* win, int base, int 
     }
 }
 
+// Both sites of a BCC trial (active site of basis B at `ba`, its partner of
+// the other basis at `bb`): the same counts as two count_uniform calls, with
+// the window reads software-pipelined over the 2S (site, shell) groups: the
+// reads of the next group are issued before the current group's counter
+// chain, so one group's LDS latency overlaps another's adds instead of every
+// group waiting for its own reads (scheduling barriers keep that order).
+template <int LAT, int B, bool PLANAR, typename CT>
+__device__ __forceinline__ void count_pair(const uint8_t* win, int ba, int bb, int LP, int PL, int CP, int S,
+                                           CT (&A)[kMaxShells], CT (&Bc)[kMaxShells])
+{
+    constexpr Geometry G = kGeom[LAT];
+    constexpr int BB = 1 - B;
+    const int XS = PLANAR ? 1 : G.m, BS = PLANAR ? CP : 1;
+    constexpr Nb mna = min_components(G, B), mnb = min_components(G, BB);
+    const int loa = mna.dz * PL + mna.dy * LP + XS * mna.dx + BS * (mna.bt - B);
+    const int lob = mnb.dz * PL + mnb.dy * LP + XS * mnb.dx + BS * (mnb.bt - BB);
+    int ra = ba + loa, rb = bb + lob;
+    asm("" : "+v"(ra), "+v"(rb));
+    const uint8_t* wa = win + ra;
+    const uint8_t* wb = win + rb;
+    uint32_t buf[2][kMaxZ];
+    // group g: site a shell g (g < kMaxShells), site b shell g - kMaxShells
+    auto load = [&](const int g, uint32_t(&v)[kMaxZ]) {
+        const int s = g % kMaxShells;
+        const int bs = g < kMaxShells ? B : BB;
+        if (s < S) {
+#pragma unroll
+            for (int n = 0; n < G.Z[s]; ++n) {
+                const Nb nb = nb_of(G, bs, G.v[s][n][0], G.v[s][n][1], G.v[s][n][2]);
+                const int off = nb.dz * PL + nb.dy * LP + XS * nb.dx + BS * (nb.bt - bs);
+                v[n] = g < kMaxShells ? wa[off - loa] : wb[off - lob];
+            }
+        }
+    };
+    auto add = [&](const int g, const uint32_t(&v)[kMaxZ]) {
+        const int s = g % kMaxShells;
+        CT acc = 0;
+        if (s < S) {
+            const int Z4 = G.Z[s] & ~3;
+#pragma unroll
+            for (int n = 0; n < Z4; n += 4) acc = shl1_add4(v[n], v[n + 1], v[n + 2], v[n + 3], acc);
+#pragma unroll
+            for (int n = Z4; n < G.Z[s]; ++n) acc = shl1_add(v[n], acc);
+        }
+        if (g < kMaxShells) A[s] = acc;
+        else Bc[s] = acc;
+    };
+    load(0, buf[0]);
+#pragma unroll
+    for (int g = 0; g < 2 * kMaxShells; ++g) {
+        if (g + 1 < 2 * kMaxShells) load(g + 1, buf[(g + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        add(g, buf[g & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // Same for the partner of an FCC site: per-lane offsets (relative to the
 // active site) from an LDS table, since the partner basis varies per lane.
 template <int LAT, typename CT>
@@ -607,11 +664,11 @@ __device__ __forceinline__ void trial_read(const SweepArgs& A, const RepDev& rep
     L.la = la;
     L.lb = la + offb;
     if (p8 == q8) return;
-    count_uniform<LAT, B, PLANAR, CT>(win, la, LP, PL, Geo::CP(rep), S, L.Ca);
     if constexpr (LAT == SMCX_BCC) {
         // the partner of a BCC site always sits on the other sublattice
-        count_uniform<LAT, 1 - B, PLANAR, CT>(win, la + offb, LP, PL, Geo::CP(rep), S, L.Cb);
+        count_pair<LAT, B, PLANAR, CT>(win, la, la + offb, LP, PL, Geo::CP(rep), S, L.Ca, L.Cb);
     } else {
+        count_uniform<LAT, B, PLANAR, CT>(win, la, LP, PL, Geo::CP(rep), S, L.Ca);
         count_table<LAT, CT>(win, la, T.offP + (B * Z1 + k) * A.sumZ, S, L.Cb);
     }
 }
@@ -647,7 +704,16 @@ __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& re
     // decision whenever that uncertainty cannot change it; otherwise the
     // binary64 sum and test below decide, as they always would.
     const int32_t* Qp = T.Q + (p * K + q);
-    uint32_t qacc = 0u - (uint32_t)T.Q[S * K * K * K + p * K + q];
+    // every table read is issued before the first product, so the trial
+    // waits for the LDS once
+    int32_t qv[kMaxShells][EN::KP];
+    const int32_t qbias = T.Q[S * K * K * K + p * K + q];
+#pragma unroll
+    for (int s = 0; s < kMaxShells; ++s)
+#pragma unroll
+        for (int tt = 0; tt < EN::KP; ++tt) qv[s][tt] = s < S && tt < K ? Qp[(s * K + tt) * K * K] : 0;
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t qacc = 0u - (uint32_t)qbias;
 #pragma unroll
     for (int s = 0; s < kMaxShells; ++s) {
         if (s < S) {
@@ -655,7 +721,7 @@ __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& re
             for (int tt = 0; tt < EN::KP; ++tt) {
                 if (tt < K) {
                     const int u = (int)((dsh[s] >> (EN::F * tt)) & EN::mask);
-                    qacc += (uint32_t)__mul24(u, Qp[(s * K + tt) * K * K]);
+                    qacc += (uint32_t)__mul24(u, qv[s][tt]);
                 }
             }
         }
