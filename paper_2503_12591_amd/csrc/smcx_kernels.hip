@@ -1336,6 +1336,16 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
         tg.c1[1] = min(tg.c0[1] + T1, rep.nc[1]);
         tg.c0[2] = gz * T2;
         tg.c1[2] = min(tg.c0[2] + T2, rep.nc[2]);
+        if constexpr (!Geo::fixed) {
+            // uneven partitions: offsets past the shorter cells leave some row
+            // groups without an active cell row; skip them before staging
+            bool any_y = false, any_z = false;
+            for (int c = tg.c0[1]; c < tg.c1[1]; ++c)
+                any_y |= cell_origin<Geo>(A, rep, 1, c + 1) - cell_origin<Geo>(A, rep, 1, c) > oy;
+            for (int c = tg.c0[2]; c < tg.c1[2]; ++c)
+                any_z |= cell_origin<Geo>(A, rep, 2, c + 1) - cell_origin<Geo>(A, rep, 2, c) > oz;
+            if (!(any_y && any_z)) continue;
+        }
         tg.w0[0] = -kHalo;
         tg.n[0] = rep.L[0] + 2 * kHalo;
         tg.gx0 = 0;
