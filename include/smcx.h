@@ -70,7 +70,8 @@ extern "C" {
 #define SMCX_FCC 1
 
 /* sweep execution modes (all give the same trajectory) */
-#define SMCX_MODE_AUTO 0        /* persistent when R > 1 or the lattice is small, else stream */
+#define SMCX_MODE_AUTO 0        /* persistent for lattices of at most 65536 sites, else stream where
+                                   row windows apply or R == 1, else persistent */
 #define SMCX_MODE_STREAM 1      /* one launch per mini-step, batched over replicas */
 #define SMCX_MODE_PERSISTENT 2  /* one launch for all sweeps, one workgroup per replica */
 #define SMCX_MODE_PLAIN 3       /* one launch per replica per mini-step (baseline loop) */

@@ -637,6 +637,7 @@ int smcx_lattice_init(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_de
             D.L[a] = R.L[a];
             D.nc[a] = (int)R.edges[a].size();
             D.M[a] = R.M[a];
+            D.emin[a] = *std::min_element(R.edges[a].begin(), R.edges[a].end());
             D.ntile[a] = R.ntile[a];
         }
         D.nA = R.nA;
@@ -1026,8 +1027,13 @@ static int run_sweeps(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t
     // index from it and first_sweep counts from 0
     if (sweep_counter) first_sweep = 0;
     const Plan& P = h->P;
+    // auto: one persistent launch for lattices too small to fill a launch per
+    // mini-step group; row windows where they apply (the ladder of 256 BCC
+    // replicas runs 10x faster in row launches than in one workgroup per
+    // replica); otherwise persistent for several replicas
     if (mode == SMCX_MODE_AUTO)
-        mode = (P.R > 1 || P.total_sites <= (1 << 16)) ? SMCX_MODE_PERSISTENT : SMCX_MODE_STREAM;
+        mode = P.total_sites <= (1 << 16) ? SMCX_MODE_PERSISTENT
+                                          : (P.rows || P.R == 1 ? SMCX_MODE_STREAM : SMCX_MODE_PERSISTENT);
     // the row kernel reads basis-planar rows; replicas of different
     // decompositions share its launches only over whole sweeps
     const bool rows = mode == SMCX_MODE_STREAM && P.rows && (!P.rows_mixed || (tau_begin == 0 && tau_end >= P.max_nA));

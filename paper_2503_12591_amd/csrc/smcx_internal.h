@@ -152,6 +152,7 @@ struct RepDev {
     int32_t L[3];        // conventional cells per axis
     int32_t nc[3];       // link cells per axis
     int32_t M[3];        // largest link-cell edge per axis
+    int32_t emin[3];     // smallest link-cell edge per axis
     int32_t nA;          // mini-steps per sweep
     int32_t ntile[3];    // tiles per axis
     int32_t cs_off;      // cell-origin table offset (x: nc0+1 entries, then y, then z)

@@ -1336,7 +1336,7 @@ __global__ __launch_bounds__(MAXB) void k_rows(SweepArgs A)
         tg.c1[1] = min(tg.c0[1] + T1, rep.nc[1]);
         tg.c0[2] = gz * T2;
         tg.c1[2] = min(tg.c0[2] + T2, rep.nc[2]);
-        if constexpr (!Geo::fixed) {
+        if (oy >= rep.emin[1] || oz >= rep.emin[2]) {
             // uneven partitions: offsets past the shorter cells leave some row
             // groups without an active cell row; skip them before staging
             bool any_y = false, any_z = false;
@@ -1787,6 +1787,176 @@ __global__ __launch_bounds__(kBlock) void k_pair_counts_tiled(const uint8_t* occ
                 H[k][2 * j] = k < K ? wave_sum(acc[k][s][j] & 0xFFFFu) : 0u;
                 H[k][2 * j + 1] = k < K ? wave_sum(acc[k][s][j] >> 16) : 0u;
             }
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int l = k; l < 4; ++l) {
+                    const uint32_t c = H[k][l] + H[l][k];
+                    if (l >= K || c == 0) continue;
+                    atomicAdd((unsigned long long*)&C[(s * K + k) * K + l], (unsigned long long)c);
+                    if (l != k) atomicAdd((unsigned long long*)&C[(s * K + l) * K + k], (unsigned long long)c);
+                }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pair counts of up to 4 species over slabs of whole x-rows: a workgroup owns
+// kSlabY consecutive rows (all of x) and a run of planes along z, and walks
+// the planes with a ring of 4 window planes in LDS: planes z .. z + 2 are
+// read while plane z + 3 comes in through registers.  Each site counts one
+// direction of every +-d pair, the one with d_z > 0 (or d_z = 0 and d_y > 0,
+// or d_z = d_y = 0 and d_x > 0), so its neighbours lie in planes z .. z + 2,
+// rows y - 2 .. y + 2 and cells x - 2 .. x + 2; as in the tiled kernel these
+// half-shell counts H give C[k][l] = H[k][l] + H[l][k].  Every byte of the
+// lattice is read (kSlabY + 4) / kSlabY times plus the ring's two extra planes
+// per run, instead of the tiles' 2-3x halo re-reads.  Planes come in by
+// LDS-direct loads while the previous plane is counted, then are scaled in
+// place to 8 * species (a neighbour costs one LDS byte read and one
+// shift-add); a site's
+// histogram goes into 16-bit fields of its species' accumulators by 24-bit
+// multiply-adds with a 0/1 factor.
+// ---------------------------------------------------------------------------
+constexpr int kSlabY = 8;
+constexpr int kSlabBlock = 512;
+
+// Positive half of shell s of a basis-b site as (dz, dy, dx, bt), in shell order.
+constexpr bool positive(const int (&v)[3]) { return v[2] > 0 || (v[2] == 0 && (v[1] > 0 || (v[1] == 0 && v[0] > 0))); }
+
+template <int LAT>
+__global__ __launch_bounds__(kSlabBlock) void k_pair_counts_slab(const uint8_t* occ, int64_t N, int L0, int L1, int L2,
+                                                               int K, int S, int ZC, int pitch, int64_t* counts)
+{
+    constexpr Geometry G = kGeom[LAT];
+    constexpr int m = G.m;
+    constexpr int NR = kSlabY + 4;
+    extern __shared__ __align__(16) uint8_t win[];  // 4 planes x NR rows x pitch
+    const int plane_bytes = NR * pitch;
+    const uint8_t* o = occ + (int64_t)blockIdx.z * N;
+    const int y0 = blockIdx.x * kSlabY;
+    const int z0 = blockIdx.y * ZC, z1 = min(z0 + ZC, L2);
+    const int rowd = (L0 * m) >> 2;  // dwords of a natural row
+    constexpr int hd = m / 2;        // dwords of a 2-cell halo
+    const int nd = rowd + 2 * hd;    // dwords of a window row: cells -2 .. L0 + 1
+    const int nitems = NR * nd;
+    auto wrap = [](int v, int L) {
+        v %= L;
+        return v < 0 ? v + L : v;
+    };
+    // plane z into ring slot `slot`: window row rr is natural row y0 - 2 + rr
+    // (wrapped), dword j of it the natural dword of cell 2 j / m - 2 (wrapped);
+    // copied straight into LDS, a wave per window row, 64 dwords per load
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    auto stage = [&](int z, int slot) {
+        const int zw = wrap(z, L2);
+        uint8_t* base = win + slot * plane_bytes;
+        for (int rr = wave; rr < NR; rr += kSlabBlock / 64) {
+            const int y = wrap(y0 - kHalo + rr, L1);
+            const uint32_t* row = (const uint32_t*)(o + (int64_t)m * L0 * (y + (int64_t)L1 * zw));
+            for (int cb = 0; cb < nd; cb += 64) {
+                const int j = cb + lane;
+                if (j < nd) {
+                    const int jj = j < hd ? rowd - hd + j : (j < hd + rowd ? j - hd : j - hd - rowd);
+                    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(row + jj),
+                                                     (__attribute__((address_space(3))) void*)(base + rr * pitch + 4 * cb),
+                                                     4, 0, 0);
+                }
+            }
+        }
+    };
+    // species -> 8 * species in place (species < 4: no byte overflows)
+    auto scale = [&](int slot) {
+        uint8_t* base = win + slot * plane_bytes;
+        for (int i = threadIdx.x; i < nitems; i += kSlabBlock) {
+            const int rr = i / nd, j = i - rr * nd;
+            uint32_t* w = (uint32_t*)(base + rr * pitch + 4 * j);
+            *w = *w << 3;
+        }
+    };
+    // accumulators: [species][shell][fields l = 0, 2 | 1, 3] with 16-bit fields
+    uint32_t acc[4][kMaxShells][2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int s = 0; s < kMaxShells; ++s) acc[k][s][0] = acc[k][s][1] = 0;
+    stage(z0, 0);
+    stage(z0 + 1, 1);
+    stage(z0 + 2, 2);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    scale(0);
+    scale(1);
+    scale(2);
+    __syncthreads();
+    const int ny = min(kSlabY, L1 - y0);
+    const int ncells = ny * L0;
+    for (int z = z0; z < z1; ++z) {
+        const bool more = z + 3 < z1 + 2;  // planes up to z1 + 1 are read
+        const int sl = z - z0;
+        if (more) stage(z + 3, (sl + 3) & 3);  // in flight while plane z is counted
+        const int pb0 = ((sl + 0) & 3) * plane_bytes, pb1 = ((sl + 1) & 3) * plane_bytes,
+                  pb2 = ((sl + 2) & 3) * plane_bytes;
+        int ly = threadIdx.x / L0, x = threadIdx.x - ly * L0;
+        const int dly = kSlabBlock / L0, dx = kSlabBlock - dly * L0;
+        for (int c = threadIdx.x; c < ncells; c += kSlabBlock) {
+            const int cell = (ly + kHalo) * pitch + (x + kHalo) * m;
+#pragma unroll
+            for (int b = 0; b < m; ++b) {
+                const int k8 = win[pb0 + cell + b];
+                uint32_t e[4];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) e[kk] = k8 == 8 * kk ? 1u : 0u;
+#pragma unroll
+                for (int s = 0; s < kMaxShells; ++s) {
+                    if (s < S) {
+                        uint32_t h = 0;
+#pragma unroll
+                        for (int n = 0; n < G.Z[s]; ++n) {
+                            if (!positive(G.v[s][n])) continue;
+                            const Nb nb = nb_of(G, b, G.v[s][n][0], G.v[s][n][1], G.v[s][n][2]);
+                            const int pbz = nb.dz == 0 ? pb0 : (nb.dz == 1 ? pb1 : pb2);
+                            h = shl1_add(win[pbz + cell + nb.dy * pitch + nb.dx * m + nb.bt], h);
+                        }
+                        // 8-bit fields (<= 12 each) -> two words of 16-bit fields
+                        const uint32_t lo = h & 0x00FF00FFu, hi = (h >> 8) & 0x00FF00FFu;
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) {
+                            acc[kk][s][0] = __umul24(lo, e[kk]) + acc[kk][s][0];
+                            acc[kk][s][1] = __umul24(hi, e[kk]) + acc[kk][s][1];
+                        }
+                    }
+                }
+                // one site's reads at a time: registers for two workgroups per CU
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            ly += dly;
+            x += dx;
+            if (x >= L0) {
+                x -= L0;
+                ++ly;
+            }
+        }
+        if (more) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            scale((sl + 3) & 3);
+        }
+        __syncthreads();
+    }
+    int64_t* C = counts + (int64_t)blockIdx.z * S * K * K;
+#pragma unroll
+    for (int s = 0; s < kMaxShells; ++s) {
+        if (s >= S) continue;
+        uint32_t H[4][4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            // fields: word 0 holds l = 0 (bits 0-15) and l = 2 (bits 16-31), word 1 l = 1 and l = 3
+            H[k][0] = k < K ? wave_sum(acc[k][s][0] & 0xFFFFu) : 0u;
+            H[k][2] = k < K ? wave_sum(acc[k][s][0] >> 16) : 0u;
+            H[k][1] = k < K ? wave_sum(acc[k][s][1] & 0xFFFFu) : 0u;
+            H[k][3] = k < K ? wave_sum(acc[k][s][1] >> 16) : 0u;
+        }
         if ((threadIdx.x & 63) == 0) {
 #pragma unroll
             for (int k = 0; k < 4; ++k)
@@ -2572,6 +2742,33 @@ hipError_t launch_advance_counter(uint32_t* counter, uint32_t n, hipStream_t st)
 hipError_t launch_pair_counts(int lattice, int K, int S, const uint8_t* occ, int64_t N, const int32_t* L,
                               int B, int64_t* counts, hipStream_t st)
 {
+    const int mm = lattice == SMCX_BCC ? 2 : 4;
+    const int nd = (L[0] * mm) / 4 + mm;  // window dwords per row of the slab kernel
+    const int slab_lds = 4 * (kSlabY + 4) * ((4 * nd + 15) & ~15);
+    if (K <= 4 && L[0] >= 48 && (L[0] * mm) % 4 == 0 && slab_lds <= 80 * 1024) {
+        // slabs of kSlabY whole rows; runs of ZC planes, enough runs for ~2048
+        // workgroups, and few enough sites per thread that every 16-bit field
+        // stays exact (a site adds at most 12 to a field)
+        const int pitch = (4 * nd + 15) & ~15;
+        const int ny = (L[1] + kSlabY - 1) / kSlabY;
+        const int per_thread = (kSlabY * L[0] + kSlabBlock - 1) / kSlabBlock * mm;  // sites per plane
+        const int zc_max = std::max(1, 5000 / per_thread);
+        int64_t runs = std::max<int64_t>(1, (2048 + (int64_t)ny * B - 1) / ((int64_t)ny * B));
+        int zc = (int)std::min<int64_t>(L[2], std::max<int64_t>(1, (L[2] + runs - 1) / runs));
+        zc = std::min(zc, zc_max);
+        const int nz = (L[2] + zc - 1) / zc;
+        if (B > 65535) return hipErrorInvalidValue;
+        const size_t lds = (size_t)4 * (kSlabY + 4) * pitch;
+        const dim3 g((unsigned)ny, (unsigned)nz, (unsigned)B), b(kSlabBlock);
+        if (lattice == SMCX_BCC) {
+            (void)hipFuncSetAttribute((const void*)k_pair_counts_slab<SMCX_BCC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(k_pair_counts_slab<SMCX_BCC>, g, b, lds, st, occ, N, L[0], L[1], L[2], K, S, zc, pitch, counts);
+        } else {
+            (void)hipFuncSetAttribute((const void*)k_pair_counts_slab<SMCX_FCC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(k_pair_counts_slab<SMCX_FCC>, g, b, lds, st, occ, N, L[0], L[1], L[2], K, S, zc, pitch, counts);
+        }
+        return hipGetLastError();
+    }
     if (K <= 4) {
         // lanes 64 x 4 cells (16 x 16 for narrow lattices), 16 cells deep;
         // at most 2048 sites per lane between flushes keeps every 16-bit

@@ -28,6 +28,8 @@ def smcx():
 @pytest.mark.parametrize("lattice,dims,K,S", [
     (BCC, (8, 8, 8), 4, 2), (BCC, (5, 6, 7), 4, 4), (FCC, (6, 5, 7), 5, 4), (BCC, (2, 2, 2), 2, 4),
     (FCC, (2, 3, 2), 3, 4), (BCC, (9, 4, 3), 8, 3), (FCC, (4, 4, 4), 8, 1), (BCC, (33, 17, 9), 2, 4),
+    # rows of 48 cells and more: whole-row slabs, rows and planes wrapping inside one slab
+    (BCC, (50, 9, 7), 4, 4), (FCC, (48, 5, 6), 3, 4), (BCC, (96, 2, 3), 2, 4), (BCC, (64, 13, 21), 4, 3),
 ])
 def test_pair_counts_energy_sro(smcx, lattice, dims, K, S):
     N = int(np.prod(dims)) * (2 if lattice == BCC else 4)
@@ -61,6 +63,17 @@ def test_pair_counts_multi_replica(smcx):
     for r in range(3):
         assert np.array_equal(C[r], O.pair_counts(BCC, dims[r], K, S, occs[r]))
     lat.close()
+
+
+@pytest.mark.parametrize("lattice,dims,K,S,B", [(BCC, (52, 6, 5), 4, 4, 3), (FCC, (48, 4, 4), 4, 4, 2)])
+def test_energy_backward_batch_wide_rows(smcx, lattice, dims, K, S, B):
+    import torch
+    N = int(np.prod(dims)) * (2 if lattice == BCC else 4)
+    occs = np.stack([rand_occ(N, K, 300 + b, equi=False) for b in range(B)])
+    say(f"energy_backward wide rows lattice={lattice} dims={dims} B={B}")
+    C = smcx.energy_backward_counts(lattice, dims, K, S, torch.from_numpy(occs).cuda()).cpu().numpy()
+    for b in range(B):
+        assert np.array_equal(C[b], O.pair_counts(lattice, dims, K, S, occs[b]))
 
 
 def test_energy_backward_batch_and_autograd(smcx):
