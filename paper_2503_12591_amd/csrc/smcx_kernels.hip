@@ -673,6 +673,54 @@ __device__ __forceinline__ void trial_read(const SweepArgs& A, const RepDev& rep
     }
 }
 
+// The decision of a trial the integer screen leaves open (a few in 1e5 at
+// the benchmark's temperature): dE summed in binary64, s and t ascending, from
+// D[s][t][p][q] (Dp points at the lane's (p, q) entry), then the float screen
+// and, where that cannot decide either, exp in binary64, the test u < P and
+// the near-tie check.  The sum starts from the first product rather than from
+// +0.0 + it: the two differ only in the sign of a zero sum, and dE <= 0
+// accepts either.  Out of line: inlined, its registers would weigh on every
+// trial's code.  Returns bit 0: accepted, bit 1: near-tie.
+template <int E>
+__device__ __noinline__ int decide_binary64(const double* Dp, typename Enc<E>::T d0, typename Enc<E>::T d1,
+                                            typename Enc<E>::T d2, typename Enc<E>::T d3, int K, int S, double beta,
+                                            uint32_t w1, uint32_t w2)
+{
+    using EN = Enc<E>;
+    using CT = typename EN::T;
+    double dE = 0.0;
+    bool first = true;
+    for (int s = 0; s < S; ++s) {
+        CT f = s == 0 ? d0 : (s == 1 ? d1 : (s == 2 ? d2 : d3));
+        const double* Ds = Dp + s * K * K * K;
+        for (int tt = 0; tt < K; ++tt) {
+            const int c = (int)(f & EN::mask) - EN::half;
+            const double term = (double)c * Ds[tt * K * K];
+            dE = first ? term : dE + term;
+            first = false;
+            f >>= EN::F;
+        }
+    }
+    if (dE <= 0.0) return 1;
+    const double x = beta * dE;
+    // A float estimate settles u < exp(-x) whenever u lies farther from it
+    // than the estimate's error: the binary64 test then gives the same answer
+    // and the trial is no near-tie.  For x <= 30, rounding x and x log2(e) to
+    // float moves the exponent by < 8e-6, so exp2 is off by < 6e-6 relative
+    // (plus an ulp or two of v_exp_f32); the margin is 1e-4 relative plus
+    // 1e-9 for u's truncation and rounding.
+    if (x > 30.0) {
+        if (w1 != 0) return 0;
+    } else {
+        const float uf = (float)w1 * 0x1p-32f;
+        const float Pf = __builtin_amdgcn_exp2f((float)x * -1.44269504f);
+        if (fabsf(uf - Pf) > 1e-4f * Pf + 1e-9f) return uf < Pf ? 1 : 0;
+    }
+    const double P = exp(-x);
+    const double u = (double)(((uint64_t)w1 << 21) | (uint64_t)(w2 >> 11)) * 0x1p-53;
+    return (u < P ? 1 : 0) | (fabs(u - P) < 1e-12 ? 2 : 0);
+}
+
 // Returns flags: bit0 active, bit1 accepted, bit2 near-tie (0 for an idle lane).
 template <int LAT, int E, class Geo>
 __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& rep, uint8_t* pad, const Lds& T,
@@ -755,54 +803,10 @@ __device__ __forceinline__ int trial_finish(const SweepArgs& A, const RepDev& re
         settled = false;
     }
     if (!settled) {
-        // the binary64 dE, s and t ascending; D[s][t][p][q]: the lanes' (p, q)
-        // entries of one term lie in one K*K*8-byte block, so their reads do
-        // not collide in LDS banks.  The sum starts from the first product
-        // rather than from +0.0 + it: the two differ only in the sign of a
-        // zero sum, and dE <= 0 accepts either.
-        const double* Dp = T.D + (p * K + q);
-        double dE;
-#pragma unroll
-        for (int s = 0; s < kMaxShells; ++s) {
-            if (s < S) {
-#pragma unroll
-                for (int tt = 0; tt < EN::KP; ++tt) {
-                    if (tt < K) {
-                        const int c = (int)((dsh[s] >> (EN::F * tt)) & EN::mask) - EN::half;
-                        const double term = (double)c * Dp[(s * K + tt) * K * K];
-                        dE = s == 0 && tt == 0 ? term : dE + term;
-                    }
-                }
-            }
-        }
-        if (dE <= 0.0) {
-            acc = true;
-        } else {
-            const double x = beta * dE;
-            // A float estimate settles u < exp(-x) whenever u lies farther
-            // from it than the estimate's error: the binary64 test then gives
-            // the same answer and the trial is no near-tie.  For x <= 30,
-            // rounding x and x log2(e) to float moves the exponent by < 8e-6,
-            // so exp2 is off by < 6e-6 relative (plus an ulp or two of
-            // v_exp_f32); the margin is 1e-4 relative plus 1e-9 for u's
-            // truncation and rounding.
-            bool fine = false;
-            if (x > 30.0) {
-                fine = L.w1 != 0;
-                acc = false;
-            } else {
-                const float uf = (float)L.w1 * 0x1p-32f;
-                const float Pf = __builtin_amdgcn_exp2f((float)x * -1.44269504f);
-                fine = fabsf(uf - Pf) > 1e-4f * Pf + 1e-9f;
-                acc = uf < Pf;
-            }
-            if (!fine) {
-                const double P = exp(-x);
-                const double u = (double)(((uint64_t)L.w1 << 21) | (uint64_t)(L.w2 >> 11)) * 0x1p-53;
-                acc = u < P;
-                tie = fabs(u - P) < 1e-12;
-            }
-        }
+        static_assert(kMaxShells == 4, "four shell counters");
+        const int f = decide_binary64<E>(T.D + (p * K + q), dsh[0], dsh[1], dsh[2], dsh[3], K, S, beta, L.w1, L.w2);
+        acc = (f & 1) != 0;
+        tie = (f & 2) != 0;
     }
     if (tie) {
         const int slot = atomicAdd(A.tie_count, 1);
