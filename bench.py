@@ -717,7 +717,8 @@ def summarize(args):
         fw, _ = _copy_factor(cwd, "WRITE_SIZE")
         names = sorted({r["Kernel_Name"] for r in _csv(fd, "counter_collection.csv") if "smcx::" in r["Kernel_Name"]})
         N = 2 * args.edge ** 3
-        algo = {"k_pair_counts_tiled": (N, 0), "k_pack": (N, None), "k_unpack": (None, N), "k_validate": (N, 0)}
+        algo = {"k_pair_counts_slab": (N, 0), "k_pair_counts_tiled": (N, 0), "k_pack": (N, None), "k_unpack": (None, N),
+                "k_validate": (N, 0)}
         lines = [f"# HBM traffic of every library kernel: BCC {args.edge}^3 benchmark, link cell {args.ell}",
                  f"# command (one pass per counter): {cmd}",
                  "# FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0 (copy-probe calibration), per dispatch; algorithmic",

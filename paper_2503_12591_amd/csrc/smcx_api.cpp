@@ -819,10 +819,10 @@ int smcx_lattice_destroy(smcx_lattice* h)
         if (g_static_owner[h->static_dev] == h) g_static_owner[h->static_dev] = nullptr;
     }
     for (auto& pr : h->pending) {
-        hipEventDestroy(pr.first);
-        hipEventDestroy(pr.second);
+        (void)hipEventDestroy(pr.first);  // teardown: nothing to report to
+        (void)hipEventDestroy(pr.second);
     }
-    for (hipEvent_t e : h->pool) hipEventDestroy(e);
+    for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     delete h;
     return SMCX_OK;
 }
@@ -1427,16 +1427,16 @@ int smcx_ladder_capture(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, const 
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(st, &graph);
     if (rc != SMCX_OK) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);  // the capture error is the one reported
         return rc;
     }
     if (e != hipSuccess || e2 != hipSuccess) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return fail(SMCX_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
     }
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);  // the executable graph keeps what it needs
     if (e != hipSuccess) return fail(SMCX_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     *graph_out = (void*)exec;
     return SMCX_OK;
@@ -1462,16 +1462,16 @@ int smcx_sweep_capture(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, const d
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(st, &graph);
     if (rc != SMCX_OK) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);  // the capture error is the one reported
         return rc;
     }
     if (e != hipSuccess || e2 != hipSuccess) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return fail(SMCX_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
     }
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);  // the executable graph keeps what it needs
     if (e != hipSuccess) return fail(SMCX_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     *graph_out = (void*)exec;
     return SMCX_OK;

@@ -1948,29 +1948,42 @@ __global__ __launch_bounds__(kSlabBlock) void k_pair_counts_slab(const uint8_t* 
         }
         __syncthreads();
     }
-    int64_t* C = counts + (int64_t)blockIdx.z * S * K * K;
+    // wave sums of H[s][k][l] into LDS (the window is free after the last
+    // barrier), the workgroup's totals, then one atomic per directed count:
+    // a few dozen atomics per workgroup instead of that many per wave
+    constexpr int NW = kSlabBlock / 64;
+    uint32_t* red = (uint32_t*)win;              // [NW][kMaxShells][16]
+    uint32_t* tot = red + NW * kMaxShells * 16;  // [kMaxShells][16]
 #pragma unroll
     for (int s = 0; s < kMaxShells; ++s) {
-        if (s >= S) continue;
-        uint32_t H[4][4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             // fields: word 0 holds l = 0 (bits 0-15) and l = 2 (bits 16-31), word 1 l = 1 and l = 3
-            H[k][0] = k < K ? wave_sum(acc[k][s][0] & 0xFFFFu) : 0u;
-            H[k][2] = k < K ? wave_sum(acc[k][s][0] >> 16) : 0u;
-            H[k][1] = k < K ? wave_sum(acc[k][s][1] & 0xFFFFu) : 0u;
-            H[k][3] = k < K ? wave_sum(acc[k][s][1] >> 16) : 0u;
+            const uint32_t h0 = wave_sum(acc[k][s][0] & 0xFFFFu), h2 = wave_sum(acc[k][s][0] >> 16);
+            const uint32_t h1 = wave_sum(acc[k][s][1] & 0xFFFFu), h3 = wave_sum(acc[k][s][1] >> 16);
+            if (lane == 0) {
+                uint32_t* r = red + (wave * kMaxShells + s) * 16 + 4 * k;
+                r[0] = h0;
+                r[1] = h1;
+                r[2] = h2;
+                r[3] = h3;
+            }
         }
-        if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-#pragma unroll
-                for (int l = k; l < 4; ++l) {
-                    const uint32_t c = H[k][l] + H[l][k];
-                    if (l >= K || c == 0) continue;
-                    atomicAdd((unsigned long long*)&C[(s * K + k) * K + l], (unsigned long long)c);
-                    if (l != k) atomicAdd((unsigned long long*)&C[(s * K + l) * K + k], (unsigned long long)c);
-                }
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxShells * 16) {
+        uint32_t v = 0;
+        for (int w = 0; w < NW; ++w) v += red[w * kMaxShells * 16 + threadIdx.x];
+        tot[threadIdx.x] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxShells * 16) {
+        const int s = threadIdx.x >> 4, k = (threadIdx.x >> 2) & 3, l = threadIdx.x & 3;
+        if (s < S && k < K && l < K) {
+            const uint32_t c = tot[s * 16 + 4 * k + l] + tot[s * 16 + 4 * l + k];
+            if (c != 0)
+                atomicAdd((unsigned long long*)&counts[(int64_t)blockIdx.z * S * K * K + (s * K + k) * K + l],
+                          (unsigned long long)c);
         }
     }
 }
@@ -2757,12 +2770,16 @@ hipError_t launch_pair_counts(int lattice, int K, int S, const uint8_t* occ, int
         const int ny = (L[1] + kSlabY - 1) / kSlabY;
         const int per_thread = (kSlabY * L[0] + kSlabBlock - 1) / kSlabBlock * mm;  // sites per plane
         const int zc_max = std::max(1, 5000 / per_thread);
-        int64_t runs = std::max<int64_t>(1, (2048 + (int64_t)ny * B - 1) / ((int64_t)ny * B));
+        // ~2048 workgroups for large batches, fewer (about 16k sites each)
+        // for small ones, whose cost would otherwise be staging and flushes
+        const int64_t want = std::min<int64_t>(2048, std::max<int64_t>(1, (int64_t)B * N / 16384));
+        int64_t runs = std::max<int64_t>(1, (want + (int64_t)ny * B - 1) / ((int64_t)ny * B));
         int zc = (int)std::min<int64_t>(L[2], std::max<int64_t>(1, (L[2] + runs - 1) / runs));
         zc = std::min(zc, zc_max);
         const int nz = (L[2] + zc - 1) / zc;
         if (B > 65535) return hipErrorInvalidValue;
-        const size_t lds = (size_t)4 * (kSlabY + 4) * pitch;
+        // the window, which also holds the final reduction (kSlabBlock / 64 + 1 rows of 64 words)
+        const size_t lds = std::max<size_t>((size_t)4 * (kSlabY + 4) * pitch, (kSlabBlock / 64 + 1) * 256);
         const dim3 g((unsigned)ny, (unsigned)nz, (unsigned)B), b(kSlabBlock);
         if (lattice == SMCX_BCC) {
             (void)hipFuncSetAttribute((const void*)k_pair_counts_slab<SMCX_BCC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
