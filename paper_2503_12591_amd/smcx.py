@@ -428,10 +428,12 @@ class LadderGraph:
     fixed betas per replica; every replay continues the chain (the sweep index
     lives in a device counter).  mode "persistent" captures the one-launch
     ladder (smcx_ladder_capture); other modes capture smcx_sweep's launches
-    (smcx_sweep_capture)."""
+    (smcx_sweep_capture).  The default, "stream", replays one launch per
+    mini-step group over all replicas, the faster of the two for ladders of
+    many replicas."""
 
     def __init__(self, lat: Lattice, n_sweeps: int, seed: int, betas, first_sweep: int = 0,
-                 tie_cap: int = 4096, mode: str = "persistent"):
+                 tie_cap: int = 4096, mode: str = "stream"):
         torch = lat.torch
         self.lat = lat
         b = np.ascontiguousarray(np.asarray(betas, np.float64).reshape(-1))
