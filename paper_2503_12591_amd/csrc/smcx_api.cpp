@@ -108,6 +108,26 @@ struct Plan {
     int max_nA;
 };
 
+// Worst LDS bank sharing of a row window's lanes: lanes walk x fastest, then
+// the ry rows of cells, then the rz planes of cells; a lane's site byte is
+// ell (x) + ell * prow (y) + ell * prow * wy (z) from its neighbour's, and a
+// wave's 64 lanes read 64 banks of 4 bytes.  Returns the largest number of
+// lanes of one wave in one bank (1: conflict-free).
+static int row_bank_ways(int ncx, int ry, int rz, int prow, int wy, int ell)
+{
+    const int lanes = ncx * ry * rz;
+    int worst = 1;
+    for (int w0 = 0; w0 < lanes; w0 += 64) {
+        int count[64] = {0};
+        for (int g = w0; g < std::min(lanes, w0 + 64); ++g) {
+            const int lx = g % ncx, ly = (g / ncx) % ry, lz = g / (ncx * ry);
+            const int64_t byte = (int64_t)ell * lx + (int64_t)ell * prow * (ly + (int64_t)wy * lz);
+            worst = std::max(worst, ++count[(byte >> 2) & 63]);
+        }
+    }
+    return worst;
+}
+
 int make_plan(const smcx_desc* d, Plan& P)
 {
     if (!d) return fail(SMCX_E_INVALID_ARG, "desc is NULL");
@@ -303,11 +323,31 @@ int make_plan(const smcx_desc* d, Plan& P)
         // FCC partners count through a table of window offsets, which holds one
         // column pitch; BCC partners derive theirs per replica
         P.rows_mixed = !same_m;
+        // Short rows (fewer cells than a wave has lanes) put several cell
+        // rows in one wave; their sites sit ell pitches apart in y and ell
+        // plane strides apart in z, so a pitch that is a multiple of 256
+        // bytes maps them all to the same LDS banks.  For BCC replicas of one
+        // decomposition, pitches in 16-byte steps are tried too, scored by
+        // the worst bank sharing (measured: 256 BCC 32^3 replicas 1.57e10 ->
+        // 1.74e10 swaps/s; a ladder of mixed sizes and FCC 128^3 ran slower
+        // with it, so they keep the aligned pitches).
+        std::vector<int> pitches = {(prowp + 255) & ~255, (prowp + 127) & ~127};
+        const bool short_rows = ncx < 64 && P.lattice == SMCX_BCC && same_m;
+        if (short_rows)
+            for (int t = 0; t < 8; ++t) pitches.push_back(((prowp + 15) & ~15) + 16 * t);
+        std::sort(pitches.begin(), pitches.end());
+        pitches.erase(std::unique(pitches.begin(), pitches.end()), pitches.end());
+        // x strides of the cells the replicas have (edges differ by at most one)
+        int ell_lo = 1 << 30, ell_hi = 0;
+        for (const Replica& R : P.reps)
+            for (int e : R.edges[0]) {
+                ell_lo = std::min(ell_lo, e);
+                ell_hi = std::max(ell_hi, e);
+            }
         if ((same_cp || P.lattice == SMCX_BCC) && ncx <= kMaxRowBlock)
-          for (int align : {256, 128})
+          for (int prow : pitches)
             for (int ry : {1, 2, 4, 8, 16})
                 for (int rz : {1, 2, 4, 8, 16}) {
-                    const int prow = (prowp + align - 1) & ~(align - 1);
                     const int lanes = ncx * ry * rz;
                     if (lanes > kMaxRowBlock) continue;
                     int wy = 0, wz = 0;
@@ -335,8 +375,12 @@ int make_plan(const smcx_desc* d, Plan& P)
                     const int wave_cap = block <= kBlock ? 12 : 16;  // register budget of the instantiation
                     const int wgs = std::min(160 * 1024 / lds, wave_cap / waves);
                     if (wgs < 1) continue;
+                    const int ways = short_rows ? std::max(row_bank_ways(ncx, ry, rz, prow, wy, ell_lo),
+                                                           row_bank_ways(ncx, ry, rz, prow, wy, ell_hi))
+                                                : 1;
+                    const double banks = short_rows ? 1.0 / (0.75 + 0.25 * ways) : (prow % 256 ? 0.98 : 1.0);
                     const double score = (double)lanes / block * std::min(1.0, wgs * waves / 12.0) *
-                                         (wgs == 1 ? 0.88 : 1.0) * (prow % 256 ? 0.98 : 1.0);
+                                         (wgs == 1 ? 0.88 : 1.0) * banks;
                     if (score > best_score + 1e-12 || (std::fabs(score - best_score) <= 1e-12 && winb < best_win)) {
                         best_score = score;
                         best_lanes = lanes;
