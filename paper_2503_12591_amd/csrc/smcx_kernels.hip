@@ -1806,7 +1806,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_counts_tiled(const uint8_t* occ
 }
 
 // ---------------------------------------------------------------------------
-// Pair counts of up to 4 species over slabs of whole x-rows: a workgroup owns
+// Pair counts of up to 5 species over slabs of whole x-rows: a workgroup owns
 // kSlabY consecutive rows (all of x) and a run of planes along z, and walks
 // the planes with a ring of 4 window planes in LDS: planes z .. z + 2 are
 // read while plane z + 3 comes in through registers.  Each site counts one
@@ -1817,10 +1817,10 @@ __global__ __launch_bounds__(kBlock) void k_pair_counts_tiled(const uint8_t* occ
 // lattice is read (kSlabY + 4) / kSlabY times plus the ring's two extra planes
 // per run, instead of the tiles' 2-3x halo re-reads.  Planes come in by
 // LDS-direct loads while the previous plane is counted, then are scaled in
-// place to 8 * species (a neighbour costs one LDS byte read and one
-// shift-add); a site's
-// histogram goes into 16-bit fields of its species' accumulators by 24-bit
-// multiply-adds with a 0/1 factor.
+// place to F * species, F = 8 for up to 4 species and 6 for 5 (a neighbour
+// costs one LDS byte read and one shift-add into F-bit fields, each at most
+// 12); a site's histogram goes into 16-bit fields of its species'
+// accumulators by 24-bit multiply-adds with a 0/1 factor.
 // ---------------------------------------------------------------------------
 constexpr int kSlabY = 8;
 constexpr int kSlabBlock = 512;
@@ -1828,10 +1828,13 @@ constexpr int kSlabBlock = 512;
 // Positive half of shell s of a basis-b site as (dz, dy, dx, bt), in shell order.
 constexpr bool positive(const int (&v)[3]) { return v[2] > 0 || (v[2] == 0 && (v[1] > 0 || (v[1] == 0 && v[0] > 0))); }
 
-template <int LAT>
+template <int LAT, int KF>
 __global__ __launch_bounds__(kSlabBlock) void k_pair_counts_slab(const uint8_t* occ, int64_t N, int L0, int L1, int L2,
                                                                int K, int S, int ZC, int pitch, int64_t* counts)
 {
+    static_assert(KF == 4 || KF == 5, "up to 4 species in 8-bit fields, 5 in 6-bit fields");
+    constexpr int F = KF == 5 ? 6 : 8;  // field width of the site histograms
+    constexpr int NWD = (KF + 1) / 2;   // words of 16-bit fields per species accumulator
     constexpr Geometry G = kGeom[LAT];
     constexpr int m = G.m;
     constexpr int NR = kSlabY + 4;
@@ -1869,21 +1872,26 @@ __global__ __launch_bounds__(kSlabBlock) void k_pair_counts_slab(const uint8_t* 
             }
         }
     };
-    // species -> 8 * species in place (species < 4: no byte overflows)
+    // species -> F * species in place (F * species <= 24: no byte overflows
+    // into the next)
     auto scale = [&](int slot) {
         uint8_t* base = win + slot * plane_bytes;
         for (int i = threadIdx.x; i < nitems; i += kSlabBlock) {
             const int rr = i / nd, j = i - rr * nd;
             uint32_t* w = (uint32_t*)(base + rr * pitch + 4 * j);
-            *w = *w << 3;
+            *w = F == 8 ? *w << 3 : *w * 6u;
         }
     };
-    // accumulators: [species][shell][fields l = 0, 2 | 1, 3] with 16-bit fields
-    uint32_t acc[4][kMaxShells][2];
+    // accumulators [species][shell][word] with 16-bit fields: for F = 8, word 0
+    // holds l = 0 and 2, word 1 l = 1 and 3; for F = 6, word w holds l = 2 w
+    // and 2 w + 1
+    uint32_t acc[KF][kMaxShells][NWD];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < KF; ++k)
 #pragma unroll
-        for (int s = 0; s < kMaxShells; ++s) acc[k][s][0] = acc[k][s][1] = 0;
+        for (int s = 0; s < kMaxShells; ++s)
+#pragma unroll
+            for (int w = 0; w < NWD; ++w) acc[k][s][w] = 0;
     stage(z0, 0);
     stage(z0 + 1, 1);
     stage(z0 + 2, 2);
@@ -1908,9 +1916,9 @@ __global__ __launch_bounds__(kSlabBlock) void k_pair_counts_slab(const uint8_t* 
 #pragma unroll
             for (int b = 0; b < m; ++b) {
                 const int k8 = win[pb0 + cell + b];
-                uint32_t e[4];
+                uint32_t e[KF];
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) e[kk] = k8 == 8 * kk ? 1u : 0u;
+                for (int kk = 0; kk < KF; ++kk) e[kk] = k8 == F * kk ? 1u : 0u;
 #pragma unroll
                 for (int s = 0; s < kMaxShells; ++s) {
                     if (s < S) {
@@ -1922,13 +1930,20 @@ __global__ __launch_bounds__(kSlabBlock) void k_pair_counts_slab(const uint8_t* 
                             const int pbz = nb.dz == 0 ? pb0 : (nb.dz == 1 ? pb1 : pb2);
                             h = shl1_add(win[pbz + cell + nb.dy * pitch + nb.dx * m + nb.bt], h);
                         }
-                        // 8-bit fields (<= 12 each) -> two words of 16-bit fields
-                        const uint32_t lo = h & 0x00FF00FFu, hi = (h >> 8) & 0x00FF00FFu;
+                        // F-bit fields (<= 12 each) -> words of 16-bit fields
+                        uint32_t wd[NWD];
+                        if constexpr (F == 8) {
+                            wd[0] = h & 0x00FF00FFu;
+                            wd[1] = (h >> 8) & 0x00FF00FFu;
+                        } else {
 #pragma unroll
-                        for (int kk = 0; kk < 4; ++kk) {
-                            acc[kk][s][0] = __umul24(lo, e[kk]) + acc[kk][s][0];
-                            acc[kk][s][1] = __umul24(hi, e[kk]) + acc[kk][s][1];
+                            for (int w = 0; w < NWD; ++w)
+                                wd[w] = ((h >> (12 * w)) & 0x3Fu) | (((h >> (12 * w + 6)) & 0x3Fu) << 16);
                         }
+#pragma unroll
+                        for (int kk = 0; kk < KF; ++kk)
+#pragma unroll
+                            for (int w = 0; w < NWD; ++w) acc[kk][s][w] = __umul24(wd[w], e[kk]) + acc[kk][s][w];
                     }
                 }
                 // one site's reads at a time: registers for two workgroups per CU
@@ -1952,35 +1967,33 @@ __global__ __launch_bounds__(kSlabBlock) void k_pair_counts_slab(const uint8_t* 
     // barrier), the workgroup's totals, then one atomic per directed count:
     // a few dozen atomics per workgroup instead of that many per wave
     constexpr int NW = kSlabBlock / 64;
-    uint32_t* red = (uint32_t*)win;              // [NW][kMaxShells][16]
-    uint32_t* tot = red + NW * kMaxShells * 16;  // [kMaxShells][16]
+    constexpr int KK = KF * KF;                  // H[k][l] entries of one shell
+    uint32_t* red = (uint32_t*)win;              // [NW][kMaxShells][KK]
+    uint32_t* tot = red + NW * kMaxShells * KK;  // [kMaxShells][KK]
 #pragma unroll
     for (int s = 0; s < kMaxShells; ++s) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            // fields: word 0 holds l = 0 (bits 0-15) and l = 2 (bits 16-31), word 1 l = 1 and l = 3
-            const uint32_t h0 = wave_sum(acc[k][s][0] & 0xFFFFu), h2 = wave_sum(acc[k][s][0] >> 16);
-            const uint32_t h1 = wave_sum(acc[k][s][1] & 0xFFFFu), h3 = wave_sum(acc[k][s][1] >> 16);
-            if (lane == 0) {
-                uint32_t* r = red + (wave * kMaxShells + s) * 16 + 4 * k;
-                r[0] = h0;
-                r[1] = h1;
-                r[2] = h2;
-                r[3] = h3;
+        for (int k = 0; k < KF; ++k) {
+#pragma unroll
+            for (int l = 0; l < KF; ++l) {
+                // field of l: F = 8 words hold (0, 2) and (1, 3); F = 6 words (2w, 2w + 1)
+                const int w = F == 8 ? (l & 1) : l >> 1, hi = F == 8 ? l >> 1 : l & 1;
+                const uint32_t h = wave_sum(hi ? acc[k][s][w] >> 16 : acc[k][s][w] & 0xFFFFu);
+                if (lane == 0) red[(wave * kMaxShells + s) * KK + k * KF + l] = h;
             }
         }
     }
     __syncthreads();
-    if (threadIdx.x < kMaxShells * 16) {
+    if (threadIdx.x < kMaxShells * KK) {
         uint32_t v = 0;
-        for (int w = 0; w < NW; ++w) v += red[w * kMaxShells * 16 + threadIdx.x];
+        for (int w = 0; w < NW; ++w) v += red[w * kMaxShells * KK + threadIdx.x];
         tot[threadIdx.x] = v;
     }
     __syncthreads();
-    if (threadIdx.x < kMaxShells * 16) {
-        const int s = threadIdx.x >> 4, k = (threadIdx.x >> 2) & 3, l = threadIdx.x & 3;
+    if (threadIdx.x < kMaxShells * KK) {
+        const int s = threadIdx.x / KK, k = (threadIdx.x % KK) / KF, l = threadIdx.x % KF;
         if (s < S && k < K && l < K) {
-            const uint32_t c = tot[s * 16 + 4 * k + l] + tot[s * 16 + 4 * l + k];
+            const uint32_t c = tot[s * KK + KF * k + l] + tot[s * KK + KF * l + k];
             if (c != 0)
                 atomicAdd((unsigned long long*)&counts[(int64_t)blockIdx.z * S * K * K + (s * K + k) * K + l],
                           (unsigned long long)c);
@@ -2762,7 +2775,7 @@ hipError_t launch_pair_counts(int lattice, int K, int S, const uint8_t* occ, int
     const int mm = lattice == SMCX_BCC ? 2 : 4;
     const int nd = (L[0] * mm) / 4 + mm;  // window dwords per row of the slab kernel
     const int slab_lds = 4 * (kSlabY + 4) * ((4 * nd + 15) & ~15);
-    if (K <= 4 && L[0] >= 48 && (L[0] * mm) % 4 == 0 && slab_lds <= 80 * 1024) {
+    if (K <= 5 && L[0] >= 48 && (L[0] * mm) % 4 == 0 && slab_lds <= 80 * 1024) {
         // slabs of kSlabY whole rows; runs of ZC planes, enough runs for ~2048
         // workgroups, and few enough sites per thread that every 16-bit field
         // stays exact (a site adds at most 12 to a field)
@@ -2778,16 +2791,24 @@ hipError_t launch_pair_counts(int lattice, int K, int S, const uint8_t* occ, int
         zc = std::min(zc, zc_max);
         const int nz = (L[2] + zc - 1) / zc;
         if (B > 65535) return hipErrorInvalidValue;
-        // the window, which also holds the final reduction (kSlabBlock / 64 + 1 rows of 64 words)
-        const size_t lds = std::max<size_t>((size_t)4 * (kSlabY + 4) * pitch, (kSlabBlock / 64 + 1) * 256);
+        // the window, which also holds the final reduction: a row of
+        // kMaxShells x KF^2 words per wave and one of totals
+        const int kf = K <= 4 ? 4 : 5;
+        const size_t red = (size_t)(kSlabBlock / 64 + 1) * kMaxShells * kf * kf * 4;
+        const size_t lds = std::max<size_t>((size_t)4 * (kSlabY + 4) * pitch, red);
         const dim3 g((unsigned)ny, (unsigned)nz, (unsigned)B), b(kSlabBlock);
-        if (lattice == SMCX_BCC) {
-            (void)hipFuncSetAttribute((const void*)k_pair_counts_slab<SMCX_BCC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(k_pair_counts_slab<SMCX_BCC>, g, b, lds, st, occ, N, L[0], L[1], L[2], K, S, zc, pitch, counts);
-        } else {
-            (void)hipFuncSetAttribute((const void*)k_pair_counts_slab<SMCX_FCC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(k_pair_counts_slab<SMCX_FCC>, g, b, lds, st, occ, N, L[0], L[1], L[2], K, S, zc, pitch, counts);
-        }
+        auto go = [&](const void* kern) {
+            (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            void* args[] = {(void*)&occ, (void*)&N, (void*)&L[0], (void*)&L[1], (void*)&L[2], (void*)&K, (void*)&S,
+                            (void*)&zc, (void*)&pitch, (void*)&counts};
+            return hipLaunchKernel(kern, g, b, args, lds, st);
+        };
+        hipError_t e;
+        if (lattice == SMCX_BCC)
+            e = go(kf == 4 ? (const void*)k_pair_counts_slab<SMCX_BCC, 4> : (const void*)k_pair_counts_slab<SMCX_BCC, 5>);
+        else
+            e = go(kf == 4 ? (const void*)k_pair_counts_slab<SMCX_FCC, 4> : (const void*)k_pair_counts_slab<SMCX_FCC, 5>);
+        if (e != hipSuccess) return e;
         return hipGetLastError();
     }
     if (K <= 4) {

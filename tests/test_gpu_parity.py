@@ -30,6 +30,8 @@ def smcx():
     (FCC, (2, 3, 2), 3, 4), (BCC, (9, 4, 3), 8, 3), (FCC, (4, 4, 4), 8, 1), (BCC, (33, 17, 9), 2, 4),
     # rows of 48 cells and more: whole-row slabs, rows and planes wrapping inside one slab
     (BCC, (50, 9, 7), 4, 4), (FCC, (48, 5, 6), 3, 4), (BCC, (96, 2, 3), 2, 4), (BCC, (64, 13, 21), 4, 3),
+    # five species: 6-bit fields in the slabs
+    (FCC, (48, 5, 6), 5, 4), (BCC, (50, 9, 7), 5, 4), (FCC, (56, 3, 11), 5, 2),
 ])
 def test_pair_counts_energy_sro(smcx, lattice, dims, K, S):
     N = int(np.prod(dims)) * (2 if lattice == BCC else 4)
@@ -65,7 +67,8 @@ def test_pair_counts_multi_replica(smcx):
     lat.close()
 
 
-@pytest.mark.parametrize("lattice,dims,K,S,B", [(BCC, (52, 6, 5), 4, 4, 3), (FCC, (48, 4, 4), 4, 4, 2)])
+@pytest.mark.parametrize("lattice,dims,K,S,B", [(BCC, (52, 6, 5), 4, 4, 3), (FCC, (48, 4, 4), 4, 4, 2),
+                                               (FCC, (48, 3, 5), 5, 4, 3)])
 def test_energy_backward_batch_wide_rows(smcx, lattice, dims, K, S, B):
     import torch
     N = int(np.prod(dims)) * (2 if lattice == BCC else 4)
