@@ -2567,17 +2567,37 @@ __device__ __forceinline__ int qsro_site_of(const QsroArgs& A, int x, int y, int
     return (d >> 24) + m * (xx + A.L0 * (yy + A.L1 * zz));
 }
 
-__device__ __forceinline__ double qsro_energy(const QsroArgs& A, int p, const uint64_t (&n)[kMaxShells])
+// Tables of a qSRO launch in LDS: V and W, and every fraction n / Z_s
+// (n = 0 .. Z_s), each the correctly rounded quotient, so a lookup gives the
+// value the division would.
+constexpr int kQsroFrac = kMaxZ + 1;
+struct QsroTables {
+    double V[kMaxShells * 8 * 8];
+    double W[kMaxShells * 8];
+    double F[kMaxShells * kQsroFrac];
+};
+
+__device__ __forceinline__ void qsro_tables(const QsroArgs& A, QsroTables& T)
+{
+    for (int i = threadIdx.x; i < A.S * A.K * A.K; i += blockDim.x) T.V[i] = A.V[i];
+    for (int i = threadIdx.x; i < A.S * A.K; i += blockDim.x) T.W[i] = A.W[i];
+    for (int i = threadIdx.x; i < A.S * kQsroFrac; i += blockDim.x) {
+        const int s = i / kQsroFrac, n = i - s * kQsroFrac;
+        T.F[i] = (double)n / (double)A.Z[s];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double qsro_energy(const QsroArgs& A, const QsroTables& T, int p,
+                                              const uint64_t (&n)[kMaxShells])
 {
     double acc = 0.0;
-    for (int s = 0; s < A.S; ++s) {
-        const double Zs = (double)A.Z[s];
+    for (int s = 0; s < A.S; ++s)
         for (int t = 0; t < A.K; ++t)
-            acc = acc + A.V[(s * A.K + p) * A.K + t] * ((double)(int)((n[s] >> (8 * t)) & 0xff) / Zs);
-    }
+            acc = acc + T.V[(s * A.K + p) * A.K + t] * T.F[s * kQsroFrac + (int)((n[s] >> (8 * t)) & 0xff)];
     for (int s = 0; s < A.S; ++s) {
-        const double f = (double)(int)((n[s] >> (8 * p)) & 0xff) / (double)A.Z[s];
-        acc = acc + A.W[s * A.K + p] * (f * f);
+        const double f = T.F[s * kQsroFrac + (int)((n[s] >> (8 * p)) & 0xff)];
+        acc = acc + T.W[s * A.K + p] * (f * f);
     }
     return acc;
 }
@@ -2587,6 +2607,8 @@ __global__ __launch_bounds__(64) void k_qsro_ministep(QsroArgs A)
 {
     constexpr int m = kGeom[LAT].m;
     __shared__ double term[kQsroMaxAff];
+    __shared__ QsroTables tab;
+    qsro_tables(A, tab);
     const int lane = threadIdx.x;
     const int ncell = A.ncx * A.ncy * A.ncz;
     const int32_t* ox = A.org;
@@ -2632,7 +2654,7 @@ __global__ __launch_bounds__(64) void k_qsro_ministep(QsroArgs A)
                 nb[s] = cb;
                 na[s] = ca;
             }
-            term[i] = qsro_energy(A, min(sj2, A.K - 1), na) - qsro_energy(A, min(sj, A.K - 1), nb);
+            term[i] = qsro_energy(A, tab, min(sj2, A.K - 1), na) - qsro_energy(A, tab, min(sj, A.K - 1), nb);
         }
         __syncthreads();
         if (lane == 0) {
