@@ -102,7 +102,8 @@ struct Plan {
     size_t off_reps, off_origins, off_tileoff, off_offP, off_offB, off_pd, off_D, off_Q, off_V, off_misc, off_pad, total;
     // qSRO model: affected-set and neighbour tables, V, W, Z
     size_t off_qaff, off_qnbr, off_qV, off_qW, off_qZ, off_qslots;
-    int qnaff;  // largest affected set
+    int qnaff;   // largest affected set
+    int qreach;  // cells per axis from the active site's cell to the farthest site a qSRO trial reads
     int n_origins;
     int64_t total_sites, total_tiles;
     int max_nA;
@@ -782,6 +783,20 @@ int smcx_lattice_init(smcx_lattice** out, const smcx_desc* desc, uint8_t* occ_de
                 largest = std::max(largest, (int)v.size());
             }
         h->P.qnaff = largest;
+        // reach of a trial in cells: the farthest affected site plus the
+        // farthest neighbour, per axis
+        int ra = 0, rn = 0;
+        for (int b = 0; b < P.m; ++b) {
+            for (int k = 0; k < P.Z1; ++k) {
+                const int32_t* row = qaff.data() + (size_t)(b * P.Z1 + k) * (1 + kQsroMaxAff);
+                for (int i = 0; i < row[0]; ++i)
+                    for (int sh = 0; sh < 3; ++sh) ra = std::max(ra, std::abs(((row[1 + i] >> (8 * sh)) & 0xff) - 8));
+            }
+            for (int j = 0; j < P.sumZ; ++j)
+                for (int sh = 0; sh < 3; ++sh)
+                    rn = std::max(rn, std::abs(((qnbr[(size_t)b * P.sumZ + j] >> (8 * sh)) & 0xff) - 8));
+        }
+        h->P.qreach = ra + rn;
         int32_t Zs[kMaxShells] = {0, 0, 0, 0};
         for (int sh = 0; sh < P.S; ++sh) Zs[sh] = G.Z[sh];
         SMCX_HIP(hipMemcpyAsync(h->ws + P.off_qnbr, qnbr.data(), sizeof(int32_t) * qnbr.size(), hipMemcpyHostToDevice, st));
@@ -1016,6 +1031,7 @@ int smcx_sweep_qsro(smcx_lattice* h, int32_t n_sweeps, uint64_t seed, uint32_t f
             A.L0 = R.L[0]; A.L1 = R.L[1]; A.L2 = R.L[2];
             A.K = P.K; A.S = P.S; A.Z1 = P.Z1; A.sumZ = P.sumZ; A.naff_max = kQsroMaxAff;
             A.ncx = (int)R.edges[0].size(); A.ncy = (int)R.edges[1].size(); A.ncz = (int)R.edges[2].size();
+            A.reach = P.qreach;
             A.org = origins + cs_off[r];
             A.sweep = first_sweep + (uint32_t)js;
             A.replica = (uint32_t)r;

@@ -2699,6 +2699,135 @@ __global__ __launch_bounds__(64) void k_qsro_ministep(QsroArgs A)
     }
 }
 
+// The same trial with its neighbourhood staged: the wave first copies the box
+// of (2 reach + 1)^3 cells around the active site's cell (periodic, one load
+// per cell of m bytes) into LDS, then every read of the affected sites and
+// their neighbours is an LDS byte at a fixed offset from the site's own (no
+// wrap arithmetic, no scattered L2 loads).  Each lattice site appears once in
+// the box because every edge is at least 2 reach + 1 cells; sites of the box
+// that the trial does not read may be written by other trials of the
+// mini-step meanwhile, which is harmless.  Terms, order of the sum, decision
+// and the near-tie log are those of k_qsro_ministep.
+template <int LAT>
+__global__ __launch_bounds__(64) void k_qsro_win(QsroArgs A)
+{
+    constexpr int m = kGeom[LAT].m;
+    constexpr int WMAX = 2 * kQsroMaxReach + 1;
+    using Cell = typename std::conditional<m == 4, uint32_t, uint16_t>::type;
+    __shared__ double term[kQsroMaxAff];
+    __shared__ QsroTables tab;
+    __shared__ __align__(16) uint8_t win[WMAX * WMAX * WMAX * m];
+    __shared__ int16_t nof[4 * kMaxShells * kMaxZ];  // [basis][neighbour]: window byte offset from the site
+    qsro_tables(A, tab);
+    const int lane = threadIdx.x;
+    const int Rch = A.reach, W = 2 * Rch + 1, W3 = W * W * W;
+    for (int i = lane; i < m * A.sumZ; i += 64) {
+        const int b = i / A.sumZ;
+        const int32_t d = A.nbr[i];
+        const int dx = (d & 0xff) - 8, dy = ((d >> 8) & 0xff) - 8, dz = ((d >> 16) & 0xff) - 8;
+        nof[i] = (int16_t)(((dz * W + dy) * W + dx) * m + (d >> 24) - b);
+    }
+    __syncthreads();
+    const int ncell = A.ncx * A.ncy * A.ncz;
+    const int32_t* ox = A.org;
+    const int32_t* oy = ox + A.ncx + 1;
+    const int32_t* oz = oy + A.ncy + 1;
+    const int center = ((Rch * W + Rch) * W + Rch) * m;  // byte of basis site 0 of the active site's cell
+    int att = 0, nacc = 0, ntie = 0;
+    for (int c = blockIdx.x; c < ncell; c += gridDim.x) {
+        const int cx = c % A.ncx, cy = (c / A.ncx) % A.ncy, cz = c / (A.ncx * A.ncy);
+        if (A.o0 >= ox[cx + 1] - ox[cx] || A.o1 >= oy[cy + 1] - oy[cy] || A.o2 >= oz[cz + 1] - oz[cz]) continue;
+        const int x = ox[cx] + A.o0, y = oy[cy] + A.o1, z = oz[cz] + A.o2;
+        const int a = A.b + m * (x + A.L0 * (y + A.L1 * z));
+        uint32_t w0, w1, w2, w3;
+        philox4x32_10((uint32_t)a, 0u, A.sweep, A.replica, (uint32_t)A.seed, (uint32_t)(A.seed >> 32), w0, w1, w2, w3);
+        (void)w3;
+        const int k = (int)__umulhi(w0, (uint32_t)A.Z1);
+        const int bsite = qsro_site_of(A, x, y, z, A.nbr[A.b * A.sumZ + k], m);
+        const int p = A.occ[a], q = A.occ[bsite];
+        ++att;
+        if (p == q) continue;
+        // the box: cell (x, y, z) + (wx, wy, wz) - reach, one wrap per axis (edges >= W)
+        for (int i = lane; i < W3; i += 64) {
+            const int wx = i % W, wy = (i / W) % W, wz = i / (W * W);
+            int xx = x + wx - Rch, yy = y + wy - Rch, zz = z + wz - Rch;
+            xx += xx < 0 ? A.L0 : (xx >= A.L0 ? -A.L0 : 0);
+            yy += yy < 0 ? A.L1 : (yy >= A.L1 ? -A.L1 : 0);
+            zz += zz < 0 ? A.L2 : (zz >= A.L2 ? -A.L2 : 0);
+            *(Cell*)(win + m * i) = *(const Cell*)(A.occ + m * (xx + A.L0 * (yy + A.L1 * zz)));
+        }
+        __syncthreads();
+        const int abyte = center + A.b;
+        const int bbyte = abyte + nof[A.b * A.sumZ + k];
+        const int32_t* list = A.aff + (int64_t)(A.b * A.Z1 + k) * (1 + A.naff_max);
+        const int naff = list[0];
+        for (int i = lane; i < naff; i += 64) {
+            const int32_t d = list[1 + i];
+            const int jb = d >> 24;
+            const int jbyte = center + ((((d >> 16) & 0xff) - 8) * W + (((d >> 8) & 0xff) - 8)) * W * m +
+                              ((d & 0xff) - 8) * m + jb;
+            const int sj = win[jbyte];
+            const int sj2 = jbyte == abyte ? q : (jbyte == bbyte ? p : sj);
+            uint64_t nb[kMaxShells], na[kMaxShells];
+            const int16_t* nl = nof + jb * A.sumZ;
+            int off = 0;
+            for (int s = 0; s < kMaxShells; ++s) {
+                uint64_t cb = 0, ca = 0;
+                if (s < A.S) {
+                    for (int n = 0; n < A.Z[s]; ++n) {
+                        const int xb = jbyte + nl[off + n];
+                        const int v = win[xb];
+                        const int v2 = xb == abyte ? q : (xb == bbyte ? p : v);
+                        cb += (uint64_t)1 << (8 * (v & 7));
+                        ca += (uint64_t)1 << (8 * (v2 & 7));
+                    }
+                    off += A.Z[s];
+                }
+                nb[s] = cb;
+                na[s] = ca;
+            }
+            term[i] = qsro_energy(A, tab, min(sj2, A.K - 1), na) - qsro_energy(A, tab, min(sj, A.K - 1), nb);
+        }
+        __syncthreads();
+        if (lane == 0) {
+            double dE = 0.0;
+            for (int i = 0; i < naff; ++i) dE = dE + term[i];
+            bool acc = true, tie = false;
+            if (!(dE <= 0.0)) {
+                const double P = exp(-(A.beta * dE));
+                const double u = (double)(((uint64_t)w1 << 21) | (uint64_t)(w2 >> 11)) * 0x1p-53;
+                acc = u < P;
+                tie = fabs(u - P) < 1e-12;
+            }
+            if (tie) {
+                ++ntie;
+                const int slot = atomicAdd(A.tie_count, 1);
+                if (slot < A.tie_cap) {
+                    smcx_tie e;
+                    e.replica = (int32_t)A.replica;
+                    e.sweep = A.sweep;
+                    e.site = a;
+                    e.decision = acc ? 1 : 0;
+                    e.pad = 0;
+                    A.ties[slot] = e;
+                }
+            }
+            if (acc) {
+                ++nacc;
+                A.occ[a] = (uint8_t)q;
+                A.occ[bsite] = (uint8_t)p;
+            }
+        }
+        __syncthreads();  // the terms and the box are free again
+    }
+    if (lane == 0) {
+        int64_t* slot = A.slots + 3 * (int64_t)blockIdx.x;
+        slot[0] += att;
+        slot[1] += nacc;
+        slot[2] += ntie;
+    }
+}
+
 // Sum the workgroups' counter slots into a replica's counters.
 __global__ void k_qsro_reduce(const int64_t* slots, int n, int64_t* stats)
 {
@@ -2726,10 +2855,20 @@ hipError_t launch_qsro_reduce(const int64_t* slots, int n, int64_t* stats, hipSt
 
 hipError_t launch_qsro_ministep(int lattice, const QsroArgs& A, int grid, hipStream_t st)
 {
-    if (lattice == SMCX_BCC)
-        hipLaunchKernelGGL(k_qsro_ministep<SMCX_BCC>, dim3((unsigned)grid), dim3(64), 0, st, A);
-    else
-        hipLaunchKernelGGL(k_qsro_ministep<SMCX_FCC>, dim3((unsigned)grid), dim3(64), 0, st, A);
+    // the windowed trial where the box fits the lattice and the kernel's LDS
+    // box (reach <= kQsroMaxReach), cells are aligned, and the neighbour
+    // table fits; the gather kernel otherwise
+    const int m = lattice == SMCX_BCC ? 2 : 4;
+    const int W = 2 * A.reach + 1;
+    const bool win = A.reach >= 1 && A.reach <= kQsroMaxReach && A.L0 >= W && A.L1 >= W && A.L2 >= W &&
+                     ((uintptr_t)A.occ % m) == 0 && m * A.sumZ <= 4 * kMaxShells * kMaxZ;
+    if (lattice == SMCX_BCC) {
+        if (win) hipLaunchKernelGGL(k_qsro_win<SMCX_BCC>, dim3((unsigned)grid), dim3(64), 0, st, A);
+        else hipLaunchKernelGGL(k_qsro_ministep<SMCX_BCC>, dim3((unsigned)grid), dim3(64), 0, st, A);
+    } else {
+        if (win) hipLaunchKernelGGL(k_qsro_win<SMCX_FCC>, dim3((unsigned)grid), dim3(64), 0, st, A);
+        else hipLaunchKernelGGL(k_qsro_ministep<SMCX_FCC>, dim3((unsigned)grid), dim3(64), 0, st, A);
+    }
     return hipGetLastError();
 }
 

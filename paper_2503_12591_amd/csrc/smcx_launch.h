@@ -28,6 +28,9 @@ hipError_t static_workspace(void** ptr);
 hipError_t launch_energy_grad(const int64_t* C, const double* g, int B, int SKK, double* grad, hipStream_t st);
 // Largest qSRO affected set a trial can have (entries of its LDS terms).
 constexpr int kQsroMaxAff = 256;
+// Largest reach (cells per axis) of the windowed qSRO trial: a box of
+// (2 reach + 1)^3 cells around the active site's cell.
+constexpr int kQsroMaxReach = 4;
 
 // Arguments of one qSRO mini-step launch over one replica.
 struct QsroArgs {
@@ -36,6 +39,7 @@ struct QsroArgs {
     const int32_t* org;    // cell origins: x (ncx + 1), y (ncy + 1), z (ncz + 1)
     int ncx, ncy, ncz;
     int o0, o1, o2, b;     // the mini-step's offsets and basis site
+    int reach;             // cells from the active site's cell to the farthest site a trial reads, per axis
     uint32_t sweep, replica;
     uint64_t seed;
     double beta;
