@@ -2744,10 +2744,10 @@ __global__ __launch_bounds__(64) void k_qsro_win(QsroArgs A)
         (void)w3;
         const int k = (int)__umulhi(w0, (uint32_t)A.Z1);
         const int bsite = qsro_site_of(A, x, y, z, A.nbr[A.b * A.sumZ + k], m);
+        // the box: cell (x, y, z) + (wx, wy, wz) - reach, one wrap per axis
+        // (edges >= W); its loads go out with those of the two sites, whose
+        // species may still show the trial to be void (p == q)
         const int p = A.occ[a], q = A.occ[bsite];
-        ++att;
-        if (p == q) continue;
-        // the box: cell (x, y, z) + (wx, wy, wz) - reach, one wrap per axis (edges >= W)
         for (int i = lane; i < W3; i += 64) {
             const int wx = i % W, wy = (i / W) % W, wz = i / (W * W);
             int xx = x + wx - Rch, yy = y + wy - Rch, zz = z + wz - Rch;
@@ -2756,7 +2756,9 @@ __global__ __launch_bounds__(64) void k_qsro_win(QsroArgs A)
             zz += zz < 0 ? A.L2 : (zz >= A.L2 ? -A.L2 : 0);
             *(Cell*)(win + m * i) = *(const Cell*)(A.occ + m * (xx + A.L0 * (yy + A.L1 * zz)));
         }
+        ++att;
         __syncthreads();
+        if (p == q) continue;
         const int abyte = center + A.b;
         const int bbyte = abyte + nof[A.b * A.sumZ + k];
         const int32_t* list = A.aff + (int64_t)(A.b * A.Z1 + k) * (1 + A.naff_max);
