@@ -593,13 +593,21 @@ int timed_launch(smcx_lattice* h, const void* kernel, dim3 grid, int block, size
 int pack_all(smcx_lattice* h, bool unpack, bool planar, hipStream_t st)
 {
     const Plan& P = h->P;
-    for (int r = 0; r < P.R; ++r) {
-        const Replica& R = P.reps[r];
-        // natural rows to unpack, padded rows (halo rows included) to pack
-        const int64_t nrows = unpack ? (int64_t)R.L[1] * R.L[2] : (int64_t)R.prows * (R.L[2] + 2 * kHalo);
-        SMCX_HIP(launch_pack(P.lattice, P.K, unpack, planar, h->occ, h->ws, (const RepDev*)(h->ws + P.off_reps), r,
-                             nrows, st));
+    // natural rows to unpack, padded rows (halo rows included) to pack
+    auto rows_of = [&](const Replica& R) {
+        return unpack ? (int64_t)R.L[1] * R.L[2] : (int64_t)R.prows * (R.L[2] + 2 * kHalo);
+    };
+    const RepDev* reps = (const RepDev*)(h->ws + P.off_reps);
+    if (P.R > 1 && P.R <= 65535) {
+        // every replica in one launch (a ladder's replicas are small: one
+        // launch each would cost more than their copies)
+        int64_t most = 0;
+        for (const Replica& R : P.reps) most = std::max(most, rows_of(R));
+        SMCX_HIP(launch_pack(P.lattice, P.K, unpack, planar, h->occ, h->ws, reps, -1, most, P.R, st));
+        return SMCX_OK;
     }
+    for (int r = 0; r < P.R; ++r)
+        SMCX_HIP(launch_pack(P.lattice, P.K, unpack, planar, h->occ, h->ws, reps, r, rows_of(P.reps[r]), 1, st));
     return SMCX_OK;
 }
 

@@ -1475,7 +1475,7 @@ __device__ __forceinline__ uint32_t pack_word(const RepDev& rep, const uint8_t* 
 template <int M, bool PLANAR>
 __global__ void k_pack(const uint8_t* occ, uint8_t* ws, const RepDev* reps, int r, int F)
 {
-    const RepDev& rep = reps[r];
+    const RepDev& rep = reps[r < 0 ? (int)blockIdx.y : r];  // r < 0: one replica per grid row
     uint8_t* pad = ws + rep.pad_off;
     const uint8_t* o = occ + rep.occ_off;
     const int L0 = rep.L[0], L1 = rep.L[1], L2 = rep.L[2];
@@ -1516,7 +1516,7 @@ __global__ void k_pack(const uint8_t* occ, uint8_t* ws, const RepDev* reps, int 
 template <int M, bool PLANAR>
 __global__ void k_unpack(uint8_t* occ, const uint8_t* ws, const RepDev* reps, int r, int F)
 {
-    const RepDev& rep = reps[r];
+    const RepDev& rep = reps[r < 0 ? (int)blockIdx.y : r];  // r < 0: one replica per grid row
     const uint8_t* pad = ws + rep.pad_off;
     uint8_t* o = occ + rep.occ_off;
     const int L0 = rep.L[0], L1 = rep.L[1], L2 = rep.L[2];
@@ -2100,13 +2100,16 @@ hipError_t sweep_occupancy(const void* kernel, int block, size_t lds, int* block
 }
 
 hipError_t launch_pack(int lattice, int K, bool unpack, bool planar, uint8_t* occ, uint8_t* ws,
-                       const RepDev* reps, int r, int64_t nrows, hipStream_t st)
+                       const RepDev* reps, int r, int64_t nrows, int nrep, hipStream_t st)
 {
-    // a workgroup per row (padded rows to pack, natural rows to unpack)
-    int64_t nb = nrows;
+    // a workgroup per row (padded rows to pack, natural rows to unpack) of
+    // replica r, or with r < 0 a grid row per replica (nrep of them, nrows
+    // the largest replica's rows), up to 8 rows per workgroup
+    int64_t nb = r < 0 ? (nrows + 7) / 8 : nrows;
     if (nb > 65536) nb = 65536;
     if (nb < 1) nb = 1;
-    const dim3 g((unsigned)nb), b(kBlock);
+    if (r < 0 && (nrep < 1 || nrep > 65535)) return hipErrorInvalidValue;
+    const dim3 g((unsigned)nb, r < 0 ? (unsigned)nrep : 1u), b(kBlock);
     const int F = field_bits_of(K);
     auto go = [&](auto mt, auto pt) {
         constexpr int M = decltype(mt)::value;

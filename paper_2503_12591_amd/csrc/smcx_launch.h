@@ -13,8 +13,10 @@ const void* row_kernel(int lattice, int K, int S, int block, int preset);
 hipError_t launch_sweep(const void* kernel, dim3 grid, int block, size_t lds, hipStream_t st, const SweepArgs& a);
 hipError_t set_sweep_lds_limit(const void* kernel, size_t lds);
 hipError_t sweep_occupancy(const void* kernel, int block, size_t lds, int* blocks_per_cu);
+// Natural layout <-> padded copy of replica r, or of every replica in one
+// launch when r < 0 (nrows: the largest replica's rows, nrep replicas).
 hipError_t launch_pack(int lattice, int K, bool unpack, bool planar, uint8_t* occ, uint8_t* ws,
-                       const RepDev* reps, int r, int64_t nrows, hipStream_t st);
+                       const RepDev* reps, int r, int64_t nrows, int nrep, hipStream_t st);
 hipError_t launch_validate(const uint8_t* occ, int64_t n, int K, int32_t* bad, hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
