@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--ladder-sweeps", type=int, default=20)
     ap.add_argument("--legs", type=str, default="all",
                     help="comma list of legs to run, for profiling one at a time: main (the BCC lattice "
-                         "above), ladder, tempering, anneal, qsro, fcc128, backward, clusters, cpu; "
+                         "above), ladder, tempering, anneal, qsro, fcc128, backward, paper795, clusters, cpu; "
                          "the JSON line is printed only when main runs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
@@ -267,7 +267,8 @@ def main():
     want = lambda name: legs is None or name in legs
     if not args.no_ladder:
         for name, fn in (("ladder", ladder_bench), ("tempering", tempering_bench), ("anneal", anneal_bench),
-                         ("qsro", qsro_bench), ("fcc128", fcc128_bench), ("backward", backward_bench)):
+                         ("qsro", qsro_bench), ("fcc128", fcc128_bench), ("backward", backward_bench),
+                         ("paper795", paper795_bench)):
             if want(name):
                 print(f"[bench] {name}", file=sys.stderr, flush=True)
                 out[name] = fn(args)
@@ -286,7 +287,8 @@ def side_legs(args, legs):
     """The workloads beside the headline one, each alone (for profiling)."""
     out = {}
     for name, fn in (("ladder", ladder_bench), ("tempering", tempering_bench), ("anneal", anneal_bench),
-                     ("qsro", qsro_bench), ("fcc128", fcc128_bench), ("backward", backward_bench)):
+                     ("qsro", qsro_bench), ("fcc128", fcc128_bench), ("backward", backward_bench),
+                     ("paper795", paper795_bench)):
         if name in legs:
             print(f"[bench] {name}", file=sys.stderr, flush=True)
             out[name] = fn(args)
@@ -577,6 +579,46 @@ def fcc128_bench(args, sweeps: int = 10):
     lat.close()
     return {"workload": w.name, "sites": w.N, "sweeps": sweeps, "unit": "attempted swaps/s",
             "swaps_per_s": sweeps * w.N / secs, "ms": secs * 1e3}
+
+
+def paper795_bench(args, sweeps: int = 4):
+    """The paper's own large lattice shape (Tab. 4, MoNbTaW_1B_EPI: BCC 795^3,
+    1.005e9 sites) with synthetic inputs (4 species equiatomic, V ~ N(0,
+    0.02 eV), 1200 K): (a) the paper's link cells of 3 with 2 shells (54
+    mini-steps per sweep), (b) 4 shells, whose link cells must be at least 4
+    (795 = 195 x 4 + 3 x 5: uneven cells, 250 mini-steps).  Attempted swaps/s
+    of `sweeps` timed sweeps after one warm-up sweep, and the row kernel's
+    average launch."""
+    import torch
+    from paper_2503_12591_amd import inputs as I
+    from paper_2503_12591_amd import smcx
+    out = {"unit": "attempted swaps/s", "sweeps": sweeps}
+    occ = None
+    for name, S, ell in (("s2_ell3", 2, 3), ("s4_ell4", 4, 4)):
+        w = I.paper_large_bcc(S)
+        if occ is None:
+            occ = I.occupancy_device(w.counts, seed=w.occ_seed)
+            out["sites"] = w.N
+        lat = smcx.Lattice(w.lattice, w.dims, w.K, w.S, occ.clone(), ell=ell)
+        lat.set_epi(w.V)
+        cells, nA = lat.schedule(0)
+        betas = torch.full((sweeps, 1), float(w.betas[0]), dtype=torch.float64, device="cuda")
+        lat.sweep(1, 0, betas[:1], mode="stream")
+        lat.timing(True)
+        lat.timing_read()
+        secs, _ = _timed(lambda: lat.sweep(sweeps, 0, betas, first_sweep=1, mode="stream"))
+        kern_ms, launches = lat.timing_read()
+        lat.timing(False)
+        avg_s = kern_ms / 1e3 / max(launches, 1)
+        trials_per_launch = w.N * sweeps / max(launches, 1)
+        ops = algorithmic_ops_per_trial(w.lattice, w.K, w.S)
+        out[name] = {"workload": w.name, "shells": S, "link_cell": ell, "n_ministeps": nA,
+                     "cells_per_axis": [len(c) for c in cells], "swaps_per_s": sweeps * w.N / secs,
+                     "ms_per_sweep": secs * 1e3 / sweeps, "launches_per_sweep": launches / sweeps,
+                     "avg_launch_us": avg_s * 1e6, "ops_per_trial": ops,
+                     "alu_frac": trials_per_launch * ops / avg_s / 1e12 / ALU_PEAK_TOPS}
+        lat.close()
+    return out
 
 
 def backward_bench(args):

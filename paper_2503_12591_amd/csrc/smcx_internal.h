@@ -196,6 +196,10 @@ struct RowPreset {
 };
 constexpr RowPreset kRowPresets[] = {
     {SMCX_BCC, 4, 4, 816, 1664, 5, 9, 200, 1, 2},  // 800-cell rows, link cells of 4, 1 x 2 rows per workgroup
+    // the paper's large lattice, 795-cell rows (Tab. 4): 4 shells with link
+    // cells of 4 and 5, and 2 shells with link cells of 3; one row per workgroup
+    {SMCX_BCC, 4, 4, 800, 1792, 5, 5, 198, 1, 1},
+    {SMCX_BCC, 4, 2, 800, 1792, 5, 5, 265, 1, 1},
 };
 constexpr int kNumRowPresets = sizeof(kRowPresets) / sizeof(kRowPresets[0]);
 

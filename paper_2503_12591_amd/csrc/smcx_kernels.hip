@@ -2036,13 +2036,16 @@ static const void* persistent_kernel()
 }
 
 
-// Row kernels: compile-time species / shell counts for the 4-species BCC and
-// 5-species FCC alloys with 4 shells, runtime counts otherwise.
+// Row kernels: compile-time species / shell counts for the 4-species BCC
+// alloys with 4 or 2 shells and the 5-species FCC alloy with 4 shells,
+// runtime counts otherwise.
 template <int LAT, int E, int MAXB>
 static const void* row_kernel_e(int K, int S)
 {
-    if constexpr (LAT == SMCX_BCC && E == 1)
+    if constexpr (LAT == SMCX_BCC && E == 1) {
         if (K == 4 && S == 4) return (const void*)k_rows<LAT, E, GeoRow<4, 4>, MAXB>;
+        if (K == 4 && S == 2) return (const void*)k_rows<LAT, E, GeoRow<4, 2>, MAXB>;
+    }
     if constexpr (LAT == SMCX_FCC && E == 3)
         if (K == 5 && S == 4) return (const void*)k_rows<LAT, E, GeoRow<5, 4>, MAXB>;
     return (const void*)k_rows<LAT, E, GeoRow<0, 0>, MAXB>;
@@ -2059,14 +2062,26 @@ static const void* row_kernel_b(int lattice, int K, int S)
                   : (e == 3 ? row_kernel_e<SMCX_FCC, 3, MAXB>(K, S) : row_kernel_e<SMCX_FCC, 2, MAXB>(K, S));
 }
 
+// The row kernel of compile-time row preset PI or a later one.
+template <int PI>
+static const void* row_preset_kernel(int preset)
+{
+    if constexpr (PI < kNumRowPresets) {
+        if (preset == PI) {
+            constexpr RowPreset q = kRowPresets[PI];
+            static_assert(q.K <= 4, "row presets use 8-bit fields");
+            constexpr int B = (q.rt0 * q.rt1 * q.rt2 + 63) / 64 * 64;
+            return (const void*)k_rows<q.lattice, 1, GeoRowFix<PI>, (B <= kBlock ? kBlock : kMaxRowBlock)>;
+        }
+        return row_preset_kernel<PI + 1>(preset);
+    } else {
+        return nullptr;
+    }
+}
+
 const void* row_kernel(int lattice, int K, int S, int block, int preset)
 {
-    static_assert(kNumRowPresets == 1, "row presets resolved below");
-    if (preset == 0) {
-        constexpr RowPreset q = kRowPresets[0];
-        constexpr int B = (q.rt0 * q.rt1 * q.rt2 + 63) / 64 * 64;
-        return (const void*)k_rows<q.lattice, 1, GeoRowFix<0>, (B <= kBlock ? kBlock : kMaxRowBlock)>;
-    }
+    if (preset >= 0) return row_preset_kernel<0>(preset);
     return block <= kBlock ? row_kernel_b<kBlock>(lattice, K, S) : row_kernel_b<kMaxRowBlock>(lattice, K, S);
 }
 

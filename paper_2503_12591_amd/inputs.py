@@ -176,6 +176,16 @@ def c5_large_bcc(n_sweeps: int = 50) -> Workload:
                     measure_every=10)
 
 
+def paper_large_bcc(S: int, n_sweeps: int = 5) -> Workload:
+    """The paper's large BCC lattice shape (Tab. 4, MoNbTaW_1B_EPI: 795^3
+    conventional cells, 1.005e9 sites) with synthetic inputs: 4 species
+    equiatomic, S shells of V ~ N(0, 0.02 eV), 1200 K."""
+    dims = (795, 795, 795)
+    N = n_sites(BCC, dims)
+    return Workload(f"bcc795_k4_s{S}_T1200", BCC, dims, 4, S, equiatomic(4, N),
+                    epi(4, S, 0.02, seed=5), np.full(n_sweeps, beta_of_T(1200.0)), occ_seed=3)
+
+
 @dataclass
 class Ladder:
     """Batched temperature ladder: R cubic BCC replicas of uneven edge."""

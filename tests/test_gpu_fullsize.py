@@ -8,6 +8,8 @@ configurations the benchmark times, compared site by site with the oracle.
   Warren-Cowley SRO of the result against the oracle's; local energies
   sampled and clusters by their invariants.  Then single row-kernel launches
   (one 8-mini-step group each), one of them with a forced near-tie.
+- The paper's large lattice shape, BCC 795^3: single row-kernel launches with
+  4 shells (uneven link cells of 4 and 5) and with 2 shells (link cells of 3).
 - FCC 128^3, 5 species: 50 sweeps with energy and SRO every 10 sweeps.
 - BCC 64^3: the whole 2000-sweep linear anneal 3000 -> 300 K, final
   occupancy and the pair counts of all 64 snapshots (batched backward).
@@ -159,6 +161,58 @@ def test_large_bcc_one_row_launch(smcx, bcc800, tau0, tie):
         O.run_ministeps(w.lattice, w.dims, w.K, w.S, cells, other, w.V, w.mc_seed, beta, 0, tau0, tau0 + 8,
                         replay=flip, nthreads=NTHREADS)
         assert not np.array_equal(gpu, other)
+
+
+@pytest.fixture(scope="module")
+def bcc795(smcx):
+    """The paper's large lattice shape (795^3 cells): one seeded occupancy on
+    the device and its host copy, shared by both shell counts."""
+    w = I.paper_large_bcc(4)
+    say("bcc795: generate")
+    occ0_dev = I.occupancy_device(w.counts, seed=w.occ_seed)
+    yield occ0_dev, occ0_dev.cpu().numpy()
+
+
+# (shells, link cell, first mini-step): with 4 shells the cells are 4 and 5
+# (195 + 3 per axis, 250 mini-steps, groups of 10); with 2 shells all are 3
+# (54 mini-steps, groups of 6).  Groups: the first, one past the shorter
+# cells (o_y = 4: only the rows of the cells of 5 are active), the last.
+@pytest.mark.parametrize("S,ell,tau0", [(4, 4, 0), (4, 4, 40), (4, 4, 240), (2, 3, 0), (2, 3, 24), (2, 3, 48)])
+def test_paper_lattice_one_row_launch(smcx, bcc795, S, ell, tau0):
+    """One row-kernel launch (every mini-step of one (o_y, o_z) group) on the
+    paper's 795^3 lattice shape, site by site against the oracle."""
+    occ0_dev, occ0 = bcc795
+    w = I.paper_large_bcc(S)
+    work = occ0_dev.clone()
+    lat = smcx.Lattice(w.lattice, w.dims, w.K, w.S, work, ell=ell)
+    try:
+        lat.set_epi(w.V)
+        cells, nA = lat.schedule(0)
+        if S == 4:
+            assert nA == 250 and sorted(set(cells[0])) == [4, 5] and list(cells[0]).count(5) == 3
+        else:
+            assert nA == 54 and [list(c) for c in cells] == [[3] * 265] * 3
+        g = 2 * max(cells[0])  # mini-steps of one (o_y, o_z) group
+        beta = float(w.betas[0])
+        say(f"bcc795 S={S} ell={ell}: row launch tau {tau0}..{tau0 + g}")
+        lat.timing(True)
+        lat.timing_read()
+        stats, ties, tc = lat.sweep_partial(0, tau0, tau0 + g, w.mc_seed, [beta], mode="stream")
+        _, launches = lat.timing_read()
+        lat.timing(False)
+        assert launches == 1
+        gpu = work.cpu().numpy()
+        tnp, nt = lat.ties_to_numpy(ties, tc)
+        s = stats.cpu().numpy()
+    finally:
+        lat.close()
+    del work
+    ref = occ0.copy()
+    res = O.run_ministeps(w.lattice, w.dims, w.K, w.S, cells, ref, w.V, w.mc_seed, beta, 0, tau0, tau0 + g,
+                          replay=tnp, nthreads=NTHREADS)
+    assert s[0] == res.stats[0] > 0
+    assert s[1] == res.stats[1] and s[2] == res.stats[2] == nt
+    assert np.array_equal(gpu, ref), f"{int((gpu != ref).sum())} sites differ"
 
 
 def test_fcc128_50_sweeps_energy_sro_every_10(smcx):
