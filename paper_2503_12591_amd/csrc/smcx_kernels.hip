@@ -2037,8 +2037,9 @@ static const void* persistent_kernel()
 
 
 // Row kernels: compile-time species / shell counts for the 4-species BCC
-// alloys with 4 or 2 shells and the 5-species FCC alloy with 4 shells,
-// runtime counts otherwise.
+// and 5-species FCC alloys with 4 or 2 shells, runtime counts otherwise (at
+// about half the speed: the 2-shell BCC lattice of 795^3 cells ran 2.2x
+// faster with its counts fixed).
 template <int LAT, int E, int MAXB>
 static const void* row_kernel_e(int K, int S)
 {
@@ -2046,8 +2047,10 @@ static const void* row_kernel_e(int K, int S)
         if (K == 4 && S == 4) return (const void*)k_rows<LAT, E, GeoRow<4, 4>, MAXB>;
         if (K == 4 && S == 2) return (const void*)k_rows<LAT, E, GeoRow<4, 2>, MAXB>;
     }
-    if constexpr (LAT == SMCX_FCC && E == 3)
+    if constexpr (LAT == SMCX_FCC && E == 3) {
         if (K == 5 && S == 4) return (const void*)k_rows<LAT, E, GeoRow<5, 4>, MAXB>;
+        if (K == 5 && S == 2) return (const void*)k_rows<LAT, E, GeoRow<5, 2>, MAXB>;
+    }
     return (const void*)k_rows<LAT, E, GeoRow<0, 0>, MAXB>;
 }
 

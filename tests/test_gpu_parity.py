@@ -187,6 +187,7 @@ def test_trajectories_varied_geometry(smcx, lattice, dims, K, S, ell, tile, mode
     (BCC, (40, 8, 8), 4, 4, 4),       # ten cells along x, x-images in the window
     (FCC, (9, 8, 10), 5, 4, 3),       # 6-bit counters
     (BCC, (12, 9, 10), 4, 2, 3),      # two shells
+    (FCC, (10, 9, 11), 5, 2, 3),      # five species, two shells (compile-time counts)
     (FCC, (12, 12, 12), 3, 3, 4),
     (BCC, (332, 8, 8), 4, 4, 4),      # long padded rows: a wave per window row when staging
     (BCC, (327, 9, 8), 4, 4, 4),      # long rows, uneven cells
