@@ -1489,19 +1489,29 @@ __global__ void k_pack(const uint8_t* occ, uint8_t* ws, const RepDev* reps, int 
         z += z < 0 ? L2 : (z >= L2 ? -L2 : 0);
         const uint8_t* src = o + (int64_t)M * L0 * (y + (int64_t)L1 * z);
         uint32_t* dst = (uint32_t*)(pad + (int64_t)row * pitch);
-        // two basis sites, planar rows, a 4-byte aligned natural row: a word
-        // of basis b at x .. x + 3 (no wrap) is bytes b, b + 2, b + 4, b + 6 of
-        // the two aligned natural words at 2 x, and times F byte by byte
-        // (every F * species < 256, so no carry crosses a byte)
-        const bool fast = M == 2 && PLANAR && ((uintptr_t)src & 3) == 0;
+        // two basis sites, planar rows: a word of basis b at x .. x + 3 (no
+        // wrap) is bytes b, b + 2, b + 4, b + 6 of the natural row from 2 x,
+        // two natural words (or, in a row that starts 2 bytes past a word
+        // boundary -- odd L0 -- three aligned words shifted by 2 bytes), and
+        // times F byte by byte (every F * species < 256, so no carry crosses
+        // a byte)
+        const int sh = (int)((uintptr_t)src & 3);  // 0 or 2: natural rows hold an even number of bytes
+        const bool fast = M == 2 && PLANAR && (sh & 1) == 0;
         const int cpw = rep.cp >> 2;
         for (int w = threadIdx.x; w < words; w += blockDim.x) {
             if (fast) {
                 const int b = w >= cpw ? 1 : 0;
                 const int xw = 4 * (w - b * cpw) - kHalo;
-                if (xw >= 0 && xw + 3 < L0) {
-                    const uint32_t* s32 = (const uint32_t*)(src + 2 * xw);
-                    const uint32_t v = __builtin_amdgcn_perm(s32[1], s32[0], b ? 0x07050301u : 0x06040200u);
+                // every byte read lies in this natural row
+                if (xw >= 0 && xw + 3 + (sh >> 1) < L0) {
+                    const uint32_t* s32 = (const uint32_t*)(src + 2 * xw - sh);
+                    uint32_t lo = s32[0], hi = s32[1];
+                    if (sh) {
+                        const uint32_t h2 = s32[2];
+                        lo = __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)sh);
+                        hi = __builtin_amdgcn_alignbyte(h2, hi, (uint32_t)sh);
+                    }
+                    const uint32_t v = __builtin_amdgcn_perm(hi, lo, b ? 0x07050301u : 0x06040200u);
                     dst[w] = v * (uint32_t)F;
                     continue;
                 }
@@ -1526,8 +1536,8 @@ __global__ void k_unpack(uint8_t* occ, const uint8_t* ws, const RepDev* reps, in
         const int y = row % L1, z = row / L1;
         const uint8_t* src = pad + ((int64_t)(z + kHalo) * rep.prows + (y + kHalo)) * pitch;
         uint8_t* dst = o + (int64_t)n * row;
-        // two basis sites, planar rows, F = 8, 4-byte aligned rows of a whole
-        // number of words: natural word w (x = 2w, 2w + 1, both basis sites)
+        // two basis sites, planar rows, F = 8, rows of a whole number of
+        // words: natural word w (x = 2w, 2w + 1, both basis sites)
         // interleaves two bytes of each basis column, taken from the aligned
         // word holding them (x + H is even, so the pair never straddles one)
         if (M == 2 && PLANAR && F == 8 && (n & 3) == 0 && ((uintptr_t)dst & 3) == 0 && ((uintptr_t)src & 3) == 0) {
@@ -1553,6 +1563,30 @@ __global__ void k_unpack(uint8_t* occ, const uint8_t* ws, const RepDev* reps, in
                     const uint32_t sel = o | ((4 + o) << 8) | ((o + 1) << 16) | ((5 + o) << 24);
                     d32[w] = (__builtin_amdgcn_perm(bb[u], a[u], sel) >> 3) & 0x1F1F1F1Fu;
                 }
+            }
+            continue;
+        }
+        // rows of 2 mod 4 bytes (odd L0), every other one starting 2 bytes
+        // past a word boundary: the words from the first aligned byte (x =
+        // x0 + 2w, x0 + 1 + 2w), each column's byte pair taken from the two
+        // aligned words around it; the bytes before and after, one by one
+        if (M == 2 && PLANAR && F == 8 && (n & 3) == 2 && ((uintptr_t)dst & 1) == 0 && ((uintptr_t)src & 3) == 0) {
+            const int pos = (int)((4 - ((uintptr_t)dst & 3)) & 3);  // 0 or 2 bytes before the first word
+            const int nw = (n - pos) >> 2, x0 = pos >> 1;
+            uint32_t* d32 = (uint32_t*)(dst + pos);
+            for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+                const int c0 = kHalo + x0 + 2 * w, c1 = rep.cp + c0;  // bytes of (x, b = 0), (x, b = 1)
+                const uint32_t* a32 = (const uint32_t*)(src + (c0 & ~3));
+                const uint32_t* b32 = (const uint32_t*)(src + (c1 & ~3));
+                const uint32_t pa = __builtin_amdgcn_alignbyte(a32[1], a32[0], (uint32_t)(c0 & 3));
+                const uint32_t pb = __builtin_amdgcn_alignbyte(b32[1], b32[0], (uint32_t)(c1 & 3));
+                d32[w] = (__builtin_amdgcn_perm(pb, pa, 0x05010400u) >> 3) & 0x1F1F1F1Fu;
+            }
+            const int tail = pos + 4 * nw;
+            for (int j = threadIdx.x; j < n - tail + pos; j += blockDim.x) {
+                const int jj = j < pos ? j : tail + (j - pos);
+                const int x = jj >> 1, b = jj & 1;
+                dst[jj] = (uint8_t)species_of(src[row_byte<PLANAR>(rep, M, x, b)], F);
             }
             continue;
         }
