@@ -236,39 +236,41 @@ __device__ __forceinline__ void count_uniform(const uint8_t* win, int base, int 
 
 // Both sites of a BCC trial (active site of basis B at `ba`, its partner of
 // the other basis at `bb`): the same counts as two count_uniform calls, with
-// the window reads software-pipelined in chunks of four neighbours of one
-// (site, shell): the reads of chunk g + 1 are issued before chunk g's four
-// counter adds (scheduling barriers keep that order), so LDS latency overlaps
-// the adds.  Measured against (site, shell) groups of up to 24 with one group
-// in flight: chunks of 4 with one ahead 954 us per 800^3 launch, against 984
-// for the groups, 965 for chunks of 8, 960 for chunks of 4 with two ahead and
-// 972 with the order left to the compiler.
-constexpr int kPairChunk = 4;
+// the window reads software-pipelined in chunks of up to CHUNK neighbours of
+// one (site, shell): the reads of chunk g + 1 are issued before chunk g's
+// counter adds (scheduling barriers keep that order), so LDS latency
+// overlaps the adds.  Row windows (compile-time pitches in the benchmark's
+// preset) take chunks of 4: 954 us per 800^3 launch against 984 for whole
+// (site, shell) groups, 965 for chunks of 8, 960 for chunks of 4 with two in
+// flight, 972 with the order left to the compiler.  Tile windows keep whole
+// groups: with chunks of 4 their runtime-pitch address arithmetic is cut
+// into the same small pieces, and the batched tile sweeps of the ladder ran
+// 11 % slower.
 struct PairChunk {
     int site, shell, n0, n1;  // neighbours n0 .. n1 - 1 of shell `shell` of site 0 (active) or 1 (partner)
 };
 struct PairChunks {
     int n;
-    PairChunk c[2 * kMaxShells * (kMaxZ / kPairChunk + 1)];
+    PairChunk c[2 * kMaxShells * kMaxZ];
 };
-constexpr PairChunks make_pair_chunks(const Geometry& G, int S)
+constexpr PairChunks make_pair_chunks(const Geometry& G, int S, int chunk)
 {
     PairChunks P{};
     P.n = 0;
     for (int site = 0; site < 2; ++site)
         for (int s = 0; s < S; ++s)
-            for (int n0 = 0; n0 < G.Z[s]; n0 += kPairChunk) {
+            for (int n0 = 0; n0 < G.Z[s]; n0 += chunk) {
                 PairChunk c{};
                 c.site = site;
                 c.shell = s;
                 c.n0 = n0;
-                c.n1 = n0 + kPairChunk < G.Z[s] ? n0 + kPairChunk : G.Z[s];
+                c.n1 = n0 + chunk < G.Z[s] ? n0 + chunk : G.Z[s];
                 P.c[P.n++] = c;
             }
     return P;
 }
 
-template <int LAT, int B, bool PLANAR, typename CT>
+template <int LAT, int B, bool PLANAR, typename CT, int CHUNK>
 __device__ __forceinline__ void count_pair(const uint8_t* win, int ba, int bb, int LP, int PL, int CP, int S,
                                            CT (&A)[kMaxShells], CT (&Bc)[kMaxShells])
 {
@@ -283,14 +285,14 @@ __device__ __forceinline__ void count_pair(const uint8_t* win, int ba, int bb, i
     const uint8_t* wa = win + ra;
     const uint8_t* wb = win + rb;
     // every chunk of the largest shell count; chunks of shells >= S are skipped
-    constexpr PairChunks PC = make_pair_chunks(G, kMaxShells);
+    constexpr PairChunks PC = make_pair_chunks(G, kMaxShells, CHUNK);
 #pragma unroll
     for (int s = 0; s < kMaxShells; ++s) {
         A[s] = 0;
         Bc[s] = 0;
     }
-    uint32_t buf[2][kPairChunk];
-    auto load = [&](const int g, uint32_t(&v)[kPairChunk]) {
+    uint32_t buf[2][CHUNK];
+    auto load = [&](const int g, uint32_t(&v)[CHUNK]) {
         const PairChunk& c = PC.c[g];
         const int bs = c.site == 0 ? B : BB;
         if (c.shell < S) {
@@ -302,7 +304,7 @@ __device__ __forceinline__ void count_pair(const uint8_t* win, int ba, int bb, i
             }
         }
     };
-    auto add = [&](const int g, const uint32_t(&v)[kPairChunk]) {
+    auto add = [&](const int g, const uint32_t(&v)[CHUNK]) {
         const PairChunk& c = PC.c[g];
         if (c.shell < S) {
             CT acc = c.site == 0 ? A[c.shell] : Bc[c.shell];
@@ -714,7 +716,7 @@ __device__ __forceinline__ void trial_read(const SweepArgs& A, const RepDev& rep
     if (p8 == q8) return;
     if constexpr (LAT == SMCX_BCC) {
         // the partner of a BCC site always sits on the other sublattice
-        count_pair<LAT, B, PLANAR, CT>(win, la, la + offb, LP, PL, Geo::CP(rep), S, L.Ca, L.Cb);
+        count_pair<LAT, B, PLANAR, CT, Geo::rows ? 4 : kMaxZ>(win, la, la + offb, LP, PL, Geo::CP(rep), S, L.Ca, L.Cb);
     } else {
         count_uniform<LAT, B, PLANAR, CT>(win, la, LP, PL, Geo::CP(rep), S, L.Ca);
         count_table<LAT, CT>(win, la, T.offP + (B * Z1 + k) * A.sumZ, S, L.Cb);
