@@ -1532,6 +1532,61 @@ __global__ void k_pack(const uint8_t* occ, uint8_t* ws, const RepDev* reps, int 
     const int pitch = PLANAR ? rep.prowp : rep.prow;
     const int nrow = rep.prows * (L2 + 2 * kHalo);
     const int words = pitch >> 2;
+    if (M == 2 && PLANAR && (rep.cp >> 4) <= (int)blockDim.x) {
+        // Two basis sites, planar rows of 16-byte aligned columns: a thread
+        // takes 16 cells of a row (x0 = 16 j - 2 .. x0 + 15, 32 natural bytes
+        // read once as 8 aligned words, or 9 shifted by 2 bytes when the row
+        // starts 2 bytes past a word boundary) and writes both basis columns'
+        // 16 bytes with one store each; blocks that wrap or pass the row's
+        // end, and the bytes past the two columns, go word by word
+        const int nblk = rep.cp >> 4, tail0 = 2 * (rep.cp >> 2);
+        const int rows_per = (int)blockDim.x / nblk;  // at least one row per pass
+        const int lr = (int)threadIdx.x / nblk, j = (int)threadIdx.x - lr * nblk;
+        for (int row0 = blockIdx.x * rows_per; row0 < nrow; row0 += gridDim.x * rows_per) {
+            const int row = row0 + lr;
+            if (lr < rows_per && row < nrow) {
+                const int yp = row % rep.prows, zp = row / rep.prows;
+                int y = yp - kHalo, z = zp - kHalo;
+                y += y < 0 ? L1 : (y >= L1 ? -L1 : 0);
+                z += z < 0 ? L2 : (z >= L2 ? -L2 : 0);
+                const uint8_t* src = o + (int64_t)M * L0 * (y + (int64_t)L1 * z);
+                uint32_t* dst = (uint32_t*)(pad + (int64_t)row * pitch);
+                const int sh = (int)((uintptr_t)src & 3);  // 0 or 2
+                const int x0 = 16 * j - kHalo;
+                if (x0 >= 0 && x0 + 16 + (sh >> 1) <= L0) {
+                    const uint32_t* s32 = (const uint32_t*)(src + 2 * x0 - sh);
+                    uint32_t d[9];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) d[i] = s32[i];
+                    if (sh) {
+                        d[8] = s32[8];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) d[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], (uint32_t)sh);
+                    }
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        uint4 v;
+                        v.x = __builtin_amdgcn_perm(d[1], d[0], b ? 0x07050301u : 0x06040200u) * (uint32_t)F;
+                        v.y = __builtin_amdgcn_perm(d[3], d[2], b ? 0x07050301u : 0x06040200u) * (uint32_t)F;
+                        v.z = __builtin_amdgcn_perm(d[5], d[4], b ? 0x07050301u : 0x06040200u) * (uint32_t)F;
+                        v.w = __builtin_amdgcn_perm(d[7], d[6], b ? 0x07050301u : 0x06040200u) * (uint32_t)F;
+                        *(uint4*)(dst + b * (rep.cp >> 2) + 4 * j) = v;
+                    }
+                } else {
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int w = b * (rep.cp >> 2) + 4 * j + t;
+                            dst[w] = pack_word<M, PLANAR>(rep, src, w, L0, F);
+                        }
+                }
+                if (j == 0)
+                    for (int w = tail0; w < words; ++w) dst[w] = 0u;
+            }
+        }
+        return;
+    }
     for (int row = blockIdx.x; row < nrow; row += gridDim.x) {
         const int yp = row % rep.prows, zp = row / rep.prows;
         int y = yp - kHalo, z = zp - kHalo;
